@@ -1,0 +1,117 @@
+/*
+ * libstokesmg -- matrix-free multigrid for the 3D Stokes problem discretized
+ * with H(div)-conforming DG (Raviart-Thomas RT_k velocity, DG Q_k pressure,
+ * symmetric interior penalty), after Cui & Kanschat, "Multigrid methods for
+ * the Stokes problem on GPU systems" (arXiv 2410.09497).  AMD Instinct MI355X
+ * (gfx950), HIP.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Mesh: the unit cube, n^3 equal cubes per level (Sec. 2.1), n a power of two.
+ * Degree k in 1..5.  N1 = n (k+1).
+ *
+ * Vector layout (one level): [u_x | u_y | u_z | p], contiguous, no padding.
+ *   u_x[ix + (N1-1) (iy + N1 iz)]  ix = interior continuous node g-1
+ *                                  (g = 1 .. N1-1), iy, iz = cell (k+1) + Gauss index
+ *   u_y[ix + N1 (iy + (N1-1) iz)]  continuous index in y
+ *   u_z[ix + N1 (iy + N1 iz)]      continuous index in z (iz < N1-1)
+ *   p  [ix + N1 (iy + N1 iz)]      all indices discontinuous
+ * Offsets: 0, nc, 2 nc, 3 nc with nc = (N1-1) N1^2; total 3 nc + N1^3.
+ * The normal velocity nodes on the boundary are eliminated (u.n = 0 is part
+ * of the space, Sec. 2.1).  The continuous direction uses Lagrange
+ * polynomials on the k+2 Gauss-Lobatto points; the discontinuous directions
+ * and the pressure use Lagrange polynomials on the k+1 Gauss points.
+ *
+ * Operator: K = [[A, B^T], [B, 0]] with A the interior-penalty form of
+ * Eq. bilinear (penalty gamma = penalty_factor (k+1)^2 / h, interior faces
+ * gamma [u].[v] - {{d_n u}}.[v] - [u].{{d_n v}}, boundary faces
+ * 2 gamma u.v - d_n u.v - u.d_n v) and B_{PX} = -(psi_P, div phi_X)
+ * (Eq. weak_form written with the symmetric sign of Eq. block_A).
+ *
+ * Memory: every vector argument is a DEVICE pointer owned by the caller.
+ * The library allocates no device memory: the caller queries
+ * stokesmg_workspace_size() and hands a device buffer of at least that size
+ * to stokesmg_set_workspace(); the library never frees caller memory.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Every
+ * entry point is asynchronous on that stream unless stated otherwise.
+ *
+ * Errors: every int-returning call returns STOKESMG_OK (0) or a negative
+ * code; stokesmg_last_error() returns a message for the last failure on that
+ * handle.  No exception or exit() crosses this boundary.
+ */
+#ifndef STOKESMG_H
+#define STOKESMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STOKESMG_OK            0
+#define STOKESMG_EINVAL       -1   /* bad argument: level, dtype, size, aliasing, NULL */
+#define STOKESMG_EHIP         -2   /* a HIP runtime error; the message keeps its text */
+#define STOKESMG_ENOMEM       -3   /* no workspace set, or it is too small */
+#define STOKESMG_ENOTCONV     -4   /* solve reached max_it; info is still filled */
+#define STOKESMG_EUNSUPPORTED -5   /* combination not built (e.g. degree out of range) */
+
+#define STOKESMG_F64 0
+#define STOKESMG_F32 1
+
+typedef struct stokesmg stokesmg_t;
+
+typedef struct {
+    int    n_cells;         /* cells per direction on the finest level; power of two, >= 1 */
+    int    k;               /* polynomial degree, 1..5 */
+    int    n_levels;        /* levels of the hierarchy; coarsest has n_cells >> (n_levels-1) cells
+                               per direction (>= 1) */
+    double penalty_factor;  /* gamma = penalty_factor (k+1)^2 / h; 2.0 in every experiment */
+} stokesmg_config;
+
+/* Builds every level's 1D tables on the host (FP64, Sec. 2 and the
+ * separable structure of Sec. 2.2).  No device memory is touched until
+ * stokesmg_set_workspace().  Returns EINVAL for an invalid config.
+ * Caller owns *out and releases it with stokesmg_destroy(). */
+int stokesmg_create(const stokesmg_config* cfg, stokesmg_t** out);
+
+/* Releases the handle (not the caller's workspace).  NULL is ignored. */
+void stokesmg_destroy(stokesmg_t* h);
+
+/* Message of the last error on this handle ("" if none).  The string is
+ * owned by the handle and valid until the next call on it. */
+const char* stokesmg_last_error(const stokesmg_t* h);
+
+/* Number of levels, and sizes of level `level` (0 = coarsest,
+ * n_levels-1 = finest): unknowns per velocity component, pressure unknowns
+ * and total.  Any output pointer may be NULL. */
+int stokesmg_num_levels(const stokesmg_t* h);
+int stokesmg_sizes(const stokesmg_t* h, int level, int64_t* n_u_comp, int64_t* n_p, int64_t* n_total);
+
+/* Device bytes the library needs (tables and internal vectors).  The
+ * buffer passed to stokesmg_set_workspace() must be 256-byte aligned. */
+int stokesmg_workspace_size(const stokesmg_t* h, size_t* bytes);
+
+/* Hands the caller-owned device buffer to the library and uploads the
+ * tables into it (asynchronously on `stream`).  The buffer must stay alive
+ * and untouched by the caller while the handle uses it.  ENOMEM if smaller
+ * than stokesmg_workspace_size(). */
+int stokesmg_set_workspace(stokesmg_t* h, void* dev_ptr, size_t bytes, void* stream);
+
+/* y = K_level x: the matrix-free operator of Alg. 1 (cell terms, interior-
+ * face and boundary-face terms of Eq. bilinear, and both divergence blocks),
+ * evaluated through its separable form (Sec. 2.2) by one fused kernel.
+ * dtype: STOKESMG_F64 (double) or STOKESMG_F32 (float); x and y have the
+ * layout above at that level.  x and y must not overlap (EINVAL). */
+int stokes_apply(stokesmg_t* h, int level, int dtype, const void* x, void* y, void* stream);
+
+/* r = b - K_level x (the residual of Alg. 2), fused into the same kernel.
+ * r may alias neither x nor b (EINVAL). */
+int stokes_residual(stokesmg_t* h, int level, int dtype, const void* b, const void* x, void* r,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STOKESMG_H */

@@ -1,0 +1,115 @@
+"""Matrix-free H(div)-DG Stokes multigrid on MI355X (gfx950).
+
+Python face of libstokesmg: torch provides device memory and streams, the
+HIP library does every step.  ``StokesMG`` owns one library handle and its
+workspace (a torch uint8 buffer on the device).
+"""
+import ctypes
+import importlib
+
+__all__ = ["StokesMG", "F64", "F32", "StokesMGError", "load_library"]
+
+F64, F32 = 0, 1
+
+
+def load_library():
+    """The ctypes binding; raises ImportError when libstokesmg.so is not
+    built (there is no fallback path)."""
+    return importlib.import_module(__name__ + "._lib")
+
+
+_lib = None
+
+
+class StokesMGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libstokesmg error {code}: {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class StokesMG:
+    def __init__(self, n_cells, k, n_levels=None, penalty_factor=2.0, device="cuda:0"):
+        global _lib
+        _lib = load_library()
+        torch = _torch()
+        if n_levels is None:
+            n_levels = n_cells.bit_length()          # down to 1^3
+        cfg = _lib.Config(n_cells, k, n_levels, penalty_factor)
+        h = ctypes.c_void_p()
+        rc = _lib.lib.stokesmg_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != 0:
+            raise StokesMGError(rc, "stokesmg_create rejected the configuration")
+        self._h = h
+        self.n_cells, self.k, self.n_levels = n_cells, k, n_levels
+        self.device = torch.device(device)
+        nb = ctypes.c_size_t()
+        self._check(_lib.lib.stokesmg_workspace_size(h, ctypes.byref(nb)))
+        self.workspace = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            self._check(_lib.lib.stokesmg_set_workspace(h, self.workspace.data_ptr(), self.workspace.numel(),
+                                                       self._stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.lib.stokesmg_destroy(h)
+            self._h = None
+
+    def _stream(self):
+        return _torch().cuda.current_stream(self.device).cuda_stream
+
+    def _check(self, rc):
+        if rc != 0:
+            msg = _lib.lib.stokesmg_last_error(self._h).decode()
+            raise StokesMGError(rc, msg)
+
+    @staticmethod
+    def _dtype_code(t):
+        torch = _torch()
+        if t.dtype == torch.float64:
+            return F64
+        if t.dtype == torch.float32:
+            return F32
+        raise TypeError("vectors must be float64 or float32")
+
+    def sizes(self, level=-1):
+        level = level % self.n_levels
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.lib.stokesmg_sizes(self._h, level, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def ndof(self, level=-1):
+        return self.sizes(level)[2]
+
+    def _vec(self, t, level, name):
+        if not t.is_contiguous() or t.device != self.device or t.numel() != self.ndof(level):
+            raise ValueError(f"{name}: need a contiguous {self.ndof(level)}-vector on {self.device}")
+
+    def apply(self, x, y=None, level=-1):
+        """y = K x on ``level`` (default finest)."""
+        level = level % self.n_levels
+        if y is None:
+            y = _torch().empty_like(x)
+        self._vec(x, level, "x")
+        self._vec(y, level, "y")
+        self._check(_lib.lib.stokes_apply(self._h, level, self._dtype_code(x), x.data_ptr(), y.data_ptr(),
+                                          self._stream()))
+        return y
+
+    def residual(self, b, x, r=None, level=-1):
+        """r = b - K x on ``level``."""
+        level = level % self.n_levels
+        if r is None:
+            r = _torch().empty_like(x)
+        for t, nm in ((b, "b"), (x, "x"), (r, "r")):
+            self._vec(t, level, nm)
+        if not (b.dtype == x.dtype == r.dtype):
+            raise TypeError("b, x, r must share a dtype")
+        self._check(_lib.lib.stokes_residual(self._h, level, self._dtype_code(x), b.data_ptr(), x.data_ptr(),
+                                             r.data_ptr(), self._stream()))
+        return r

@@ -1,0 +1,47 @@
+"""ctypes binding of libstokesmg (include/stokesmg.h): argument marshalling
+only.  Every computation happens in the HIP library; if the library is not
+built this module raises at import."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstokesmg.so")
+
+OK, EINVAL, EHIP, ENOMEM, ENOTCONV, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+F64, F32 = 0, 1
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int), ("k", ctypes.c_int), ("n_levels", ctypes.c_int),
+                ("penalty_factor", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2410_09497_amd/build.py "
+                          "(or __graft_entry__.build()); there is no fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64p, szp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "stokesmg_create": (i32, [ctypes.POINTER(Config), ctypes.POINTER(vp)]),
+        "stokesmg_destroy": (None, [vp]),
+        "stokesmg_last_error": (ctypes.c_char_p, [vp]),
+        "stokesmg_num_levels": (i32, [vp]),
+        "stokesmg_sizes": (i32, [vp, i32, i64p, i64p, i64p]),
+        "stokesmg_workspace_size": (i32, [vp, szp]),
+        "stokesmg_set_workspace": (i32, [vp, vp, ctypes.c_size_t, vp]),
+        "stokes_apply": (i32, [vp, i32, i32, vp, vp, vp]),
+        "stokes_residual": (i32, [vp, i32, i32, vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+EXPORTED = ["stokesmg_create", "stokesmg_destroy", "stokesmg_last_error", "stokesmg_num_levels",
+            "stokesmg_sizes", "stokesmg_workspace_size", "stokesmg_set_workspace", "stokes_apply",
+            "stokes_residual"]

@@ -1,0 +1,13 @@
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace smg {
+
+// y = K x (resid = false) or y = b - K x (resid = true) on one level with
+// n cells per direction; `tab` is that level's device stencil table in the
+// same dtype.  Asynchronous on `st`.
+hipError_t launch_apply(int k, bool f64, bool resid, const void* x, const void* b, void* y,
+                        const void* tab, int n, hipStream_t st);
+
+}  // namespace smg
