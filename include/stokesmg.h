@@ -66,7 +66,11 @@ typedef struct {
     int    k;               /* polynomial degree, 1..5 */
     int    n_levels;        /* levels of the hierarchy; coarsest has n_cells >> (n_levels-1) cells
                                per direction (>= 1) */
-    double penalty_factor;  /* gamma = penalty_factor (k+1)^2 / h; 2.0 in every experiment */
+    double penalty_factor;  /* gamma = penalty_factor (k+1)^2 / h; must be 2.0, the method's value
+                               (the kernels carry it as a compile-time constant): other values
+                               return STOKESMG_EUNSUPPORTED */
+    double cg_rtol;         /* local Schur-complement CG: stop when ||r|| <= cg_rtol ||r_0|| ... */
+    int    cg_max_it;       /* ... or after cg_max_it iterations (Sec. 3.3: about 15 on average) */
 } stokesmg_config;
 
 /* Builds every level's 1D tables on the host (FP64, Sec. 2 and the
@@ -109,6 +113,23 @@ int stokes_apply(stokesmg_t* h, int level, int dtype, const void* x, void* y, vo
  * r may alias neither x nor b (EINVAL). */
 int stokes_residual(stokesmg_t* h, int level, int dtype, const void* b, const void* x, void* r,
                     void* stream);
+
+/* One or more sweeps of the colourized multiplicative vertex-patch smoother
+ * (Alg. 2) on level `level` (n >= 2 cells per direction): for each colour
+ * c = 0..7 in ascending order, r = b - K x over the whole level, then every
+ * patch j of colour c adds R_j^T A_j^{-1} R_j r to x in parallel (the DoF sets
+ * of one colour are disjoint).  The local solve is the Schur complement
+ * (Sec. 3.2): CG on S = B_j A_j^{-1} B_j^T over mean-zero patch pressures, with
+ * A_j^{-1} applied by fast diagonalization; with a tight cg_rtol it equals the
+ * pseudo-inverse solve (Sec. 3.3).  x is updated in place; b is read only.
+ * x and b must not overlap each other or the workspace (EINVAL).
+ * Degrees 1..3 (EUNSUPPORTED otherwise). */
+int patch_smooth(stokesmg_t* h, int level, int dtype, void* x, const void* b, int n_sweeps, void* stream);
+
+/* Total local CG iterations and local solves performed by patch_smooth since
+ * the last reset (reset = 1 zeroes them after reading).  Synchronizes
+ * `stream`. */
+int stokesmg_cg_stats(stokesmg_t* h, int64_t* iterations, int64_t* solves, int reset, void* stream);
 
 #ifdef __cplusplus
 }

@@ -33,18 +33,20 @@ def _torch():
 
 
 class StokesMG:
-    def __init__(self, n_cells, k, n_levels=None, penalty_factor=2.0, device="cuda:0"):
+    def __init__(self, n_cells, k, n_levels=None, penalty_factor=2.0, device="cuda:0", cg_rtol=1e-13,
+                 cg_max_it=200):
         global _lib
         _lib = load_library()
         torch = _torch()
         if n_levels is None:
             n_levels = n_cells.bit_length()          # down to 1^3
-        cfg = _lib.Config(n_cells, k, n_levels, penalty_factor)
+        cfg = _lib.Config(n_cells, k, n_levels, penalty_factor, cg_rtol, cg_max_it)
         h = ctypes.c_void_p()
         rc = _lib.lib.stokesmg_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc != 0:
             raise StokesMGError(rc, "stokesmg_create rejected the configuration")
         self._h = h
+        self._L = _lib            # keeps the library alive until this handle is released
         self.n_cells, self.k, self.n_levels = n_cells, k, n_levels
         self.device = torch.device(device)
         nb = ctypes.c_size_t()
@@ -56,8 +58,9 @@ class StokesMG:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _lib.lib.stokesmg_destroy(h)
+        L = getattr(self, "_L", None)
+        if h is not None and h.value and L is not None:
+            L.lib.stokesmg_destroy(h)
             self._h = None
 
     def _stream(self):
@@ -113,3 +116,21 @@ class StokesMG:
         self._check(_lib.lib.stokes_residual(self._h, level, self._dtype_code(x), b.data_ptr(), x.data_ptr(),
                                              r.data_ptr(), self._stream()))
         return r
+
+    def smooth(self, x, b, level=-1, sweeps=1):
+        """x <- S(x, b): ``sweeps`` colourized vertex-patch sweeps, in place."""
+        level = level % self.n_levels
+        self._vec(x, level, "x")
+        self._vec(b, level, "b")
+        if x.dtype != b.dtype:
+            raise TypeError("x and b must share a dtype")
+        self._check(_lib.lib.patch_smooth(self._h, level, self._dtype_code(x), x.data_ptr(), b.data_ptr(), sweeps,
+                                          self._stream()))
+        return x
+
+    def cg_stats(self, reset=True):
+        """(local CG iterations, local solves) since the last reset."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.lib.stokesmg_cg_stats(self._h, ctypes.byref(a), ctypes.byref(b), int(reset),
+                                               self._stream()))
+        return a.value, b.value

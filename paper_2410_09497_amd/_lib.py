@@ -13,7 +13,7 @@ F64, F32 = 0, 1
 
 class Config(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int), ("k", ctypes.c_int), ("n_levels", ctypes.c_int),
-                ("penalty_factor", ctypes.c_double)]
+                ("penalty_factor", ctypes.c_double), ("cg_rtol", ctypes.c_double), ("cg_max_it", ctypes.c_int)]
 
 
 def _load():
@@ -32,6 +32,8 @@ def _load():
         "stokesmg_set_workspace": (i32, [vp, vp, ctypes.c_size_t, vp]),
         "stokes_apply": (i32, [vp, i32, i32, vp, vp, vp]),
         "stokes_residual": (i32, [vp, i32, i32, vp, vp, vp, vp]),
+        "patch_smooth": (i32, [vp, i32, i32, vp, vp, i32, vp]),
+        "stokesmg_cg_stats": (i32, [vp, i64p, i64p, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -44,4 +46,4 @@ lib = _load()
 
 EXPORTED = ["stokesmg_create", "stokesmg_destroy", "stokesmg_last_error", "stokesmg_num_levels",
             "stokesmg_sizes", "stokesmg_workspace_size", "stokesmg_set_workspace", "stokes_apply",
-            "stokes_residual"]
+            "stokes_residual", "patch_smooth", "stokesmg_cg_stats"]

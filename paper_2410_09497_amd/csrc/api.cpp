@@ -9,6 +9,8 @@
 
 #include "apply.hpp"
 #include "handle.hpp"
+#include "patch.hpp"
+#include "patch_tables.hpp"
 #include "stencil_tables.hpp"
 
 namespace {
@@ -43,25 +45,40 @@ int stokesmg_create(const stokesmg_config* cfg, stokesmg_t** out) {
     if (n < 1 || (n & (n - 1)) != 0 || k < 1 || k > 5 || L < 1 || (n >> (L - 1)) < 1 ||
         ((n >> (L - 1)) << (L - 1)) != n || !(cfg->penalty_factor > 0))
         return STOKESMG_EINVAL;
+    // the kernels carry the method's penalty gamma = 2 (k+1)^2 / h as compile-time constants
+    if (cfg->penalty_factor != 2.0) return STOKESMG_EUNSUPPORTED;
+    if (!(cfg->cg_rtol >= 0) || cfg->cg_max_it < 0) return STOKESMG_EINVAL;
     stokesmg* h = new (std::nothrow) stokesmg;
     if (!h) return STOKESMG_ENOMEM;
     h->cfg = *cfg;
     h->n_levels = L;
     try {
         smg::Ref1D ref(k);
-        for (int l = 0; l < L; ++l) h->lv.push_back(smg::build_level_tables(ref, n >> (L - 1 - l), cfg->penalty_factor));
+        for (int l = 0; l < L; ++l) {
+            const int nl = n >> (L - 1 - l);
+            h->lv.push_back(smg::build_level_tables(ref, nl, cfg->penalty_factor));
+            h->lv.back().patch = smg::build_patch_tables(ref, nl, cfg->penalty_factor);
+        }
     } catch (const std::exception& e) {
         delete h;
         return STOKESMG_EINVAL;
     }
     size_t off = 0;
-    const size_t tsz = smg::tab_size(k);
+    const size_t tsz = smg::tab_size(k), psz = smg::patch_tab_size(k);
     for (int l = 0; l < L; ++l) {
         h->tab_f64.push_back(off);
         off = align256(off + tsz * sizeof(double));
         h->tab_f32.push_back(off);
         off = align256(off + tsz * sizeof(float));
+        h->ptab_f64.push_back(off);
+        off = align256(off + psz * sizeof(double));
+        h->ptab_f32.push_back(off);
+        off = align256(off + psz * sizeof(float));
     }
+    h->cg_counter = off;
+    off = align256(off + 2 * sizeof(int));
+    h->r_vec = off;
+    off = align256(off + size_t(level_total(h, L - 1)) * sizeof(double));
     h->ws_needed = off;
     *out = h;
     return STOKESMG_OK;
@@ -96,15 +113,21 @@ int stokesmg_set_workspace(stokesmg_t* h, void* dev_ptr, size_t bytes, void* str
     h->ws = static_cast<char*>(dev_ptr);
     h->ws_bytes = bytes;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const size_t tsz = smg::tab_size(h->cfg.k);
-    for (int l = 0; l < h->n_levels; ++l) {
-        const auto& t = h->lv[l].stencil;
+    auto upload = [&](const std::vector<double>& t, size_t o64, size_t o32) -> int {
+        if (t.empty()) return STOKESMG_OK;
         std::vector<float> tf(t.begin(), t.end());
-        SMG_HIP(h, hipMemcpyAsync(h->ws + h->tab_f64[l], t.data(), tsz * sizeof(double), hipMemcpyHostToDevice, st));
-        SMG_HIP(h, hipMemcpyAsync(h->ws + h->tab_f32[l], tf.data(), tsz * sizeof(float), hipMemcpyHostToDevice, st));
+        SMG_HIP(h, hipMemcpyAsync(h->ws + o64, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        SMG_HIP(h, hipMemcpyAsync(h->ws + o32, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice, st));
         // the host buffers die at scope exit: finish the copies first
         SMG_HIP(h, hipStreamSynchronize(st));
+        return STOKESMG_OK;
+    };
+    for (int l = 0; l < h->n_levels; ++l) {
+        if (int rc = upload(h->lv[l].stencil, h->tab_f64[l], h->tab_f32[l])) return rc;
+        if (int rc = upload(h->lv[l].patch, h->ptab_f64[l], h->ptab_f32[l])) return rc;
     }
+    SMG_HIP(h, hipMemsetAsync(h->ws + h->cg_counter, 0, 2 * sizeof(int), st));
+    SMG_HIP(h, hipStreamSynchronize(st));
     return STOKESMG_OK;
 }
 
@@ -132,6 +155,47 @@ int stokes_residual(stokesmg_t* h, int level, int dtype, const void* b, const vo
     const void* tab = h->ws + (f64 ? h->tab_f64[level] : h->tab_f32[level]);
     SMG_HIP(h, smg::launch_apply(h->cfg.k, f64, true, x, b, r, tab, h->lv[level].n,
                                  static_cast<hipStream_t>(stream)));
+    return STOKESMG_OK;
+}
+
+int patch_smooth(stokesmg_t* h, int level, int dtype, void* x, const void* b, int n_sweeps, void* stream) {
+    if (!h) return STOKESMG_EINVAL;
+    if (int rc = check_level_dtype(h, level, dtype)) return rc;
+    if (!x || !b || n_sweeps < 0) return h->fail(STOKESMG_EINVAL, "null vector or negative sweep count");
+    if (h->lv[level].n < 2) return h->fail(STOKESMG_EINVAL, "level has no interior vertex (n < 2)");
+    if (h->cfg.k > 3) return h->fail(STOKESMG_EUNSUPPORTED, "patch_smooth is built for degrees 1..3");
+    const size_t es = dtype == STOKESMG_F64 ? 8 : 4;
+    const size_t bytes = size_t(level_total(h, level)) * es;
+    if (overlap(x, b, bytes) || overlap(x, h->ws, h->ws_bytes) || overlap(b, h->ws, h->ws_bytes))
+        return h->fail(STOKESMG_EINVAL, "x, b and the workspace must not overlap");
+    const bool f64 = dtype == STOKESMG_F64;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void* r = h->ws + h->r_vec;
+    const void* tab = h->ws + (f64 ? h->tab_f64[level] : h->tab_f32[level]);
+    const void* ptab = h->ws + (f64 ? h->ptab_f64[level] : h->ptab_f32[level]);
+    int* counters = reinterpret_cast<int*>(h->ws + h->cg_counter);
+    for (int s = 0; s < n_sweeps; ++s)
+        for (int c = 0; c < 8; ++c) {
+            SMG_HIP(h, smg::launch_apply(h->cfg.k, f64, true, x, b, r, tab, h->lv[level].n, st));
+            SMG_HIP(h, smg::launch_patch_solve(h->cfg.k, f64, x, r, ptab, h->lv[level].n, c, h->cfg.cg_rtol,
+                                               h->cfg.cg_max_it, counters, st));
+        }
+    return STOKESMG_OK;
+}
+
+int stokesmg_cg_stats(stokesmg_t* h, int64_t* iterations, int64_t* solves, int reset, void* stream) {
+    if (!h) return STOKESMG_EINVAL;
+    if (!h->ws) return h->fail(STOKESMG_ENOMEM, "no workspace set");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int c[2] = {0, 0};
+    SMG_HIP(h, hipMemcpyAsync(c, h->ws + h->cg_counter, sizeof(c), hipMemcpyDeviceToHost, st));
+    SMG_HIP(h, hipStreamSynchronize(st));
+    if (iterations) *iterations = c[0];
+    if (solves) *solves = c[1];
+    if (reset) {
+        SMG_HIP(h, hipMemsetAsync(h->ws + h->cg_counter, 0, 2 * sizeof(int), st));
+        SMG_HIP(h, hipStreamSynchronize(st));
+    }
     return STOKESMG_OK;
 }
 

@@ -6,8 +6,16 @@ namespace smg {
 
 // y = K x (resid = false) or y = b - K x (resid = true) on one level with
 // n cells per direction; `tab` is that level's device stencil table in the
-// same dtype.  Asynchronous on `st`.
+// same dtype (used by the generic kernel).  Asynchronous on `st`.
 hipError_t launch_apply(int k, bool f64, bool resid, const void* x, const void* b, void* y,
                         const void* tab, int n, hipStream_t st);
+
+// one translation unit per degree (apply_k<K>.hip)
+template <int K>
+hipError_t launch_apply_k(bool f64, bool resid, const void* x, const void* b, void* y, const void* tab, int n,
+                          hipStream_t st);
+
+// workgroups per z column of tiles: >= 2048 workgroups, chunks >= 4 layers
+int apply_chunk_layers(int n, int blocks_xy);
 
 }  // namespace smg

@@ -119,3 +119,82 @@ LevelTables build_level_tables(const Ref1D& r, int n, double penalty_factor) {
 }
 
 }  // namespace smg
+
+// ------------------------------------------------------------------ patches
+#include "eig.hpp"
+#include "patch_tables.hpp"
+
+namespace smg {
+
+std::vector<double> build_patch_tables(const Ref1D& r, int n, double penalty_factor) {
+    if (n < 2) return {};
+    const int k = r.k, m = k + 1, nc = 2 * k + 1, nd = 2 * k + 2;
+    const double h = 1.0 / n;
+    std::vector<double> t(patch_tab_size(k), 0.0);
+    const int oSC = 0, oLC = nc * nc, oSD = oLC + nc, oLD = oSD + 4 * nd * nd, oDP = oLD + 4 * nd,
+              oMD = oDP + nd * nc;
+    auto check = [&](const Dense& L, const Dense& M, const std::vector<double>& lam, const Dense& S) {
+        const int q = L.rows;
+        double e = 0.0, sc = 0.0;
+        for (int i = 0; i < q; ++i) sc = std::fmax(sc, std::fabs(lam[i]));
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < q; ++j) {
+                double sm = 0.0, sl = 0.0;
+                for (int a = 0; a < q; ++a)
+                    for (int b = 0; b < q; ++b) {
+                        sm += S(a, i) * M(a, b) * S(b, j);
+                        sl += S(a, i) * L(a, b) * S(b, j);
+                    }
+                e = std::fmax(e, std::fabs(sm - (i == j ? 1.0 : 0.0)));
+                e = std::fmax(e, std::fabs(sl - (i == j ? lam[i] : 0.0)) / sc);
+            }
+        if (!(e < 1e-9)) throw std::runtime_error("patch eigen-decomposition self-check failed");
+    };
+    // continuous window: interior nodes of two cells; identical for every patch
+    {
+        Global1D g(r, 4, h, penalty_factor);
+        const int base = m;   // nodes of cells 1, 2 (interior-node indexing starts at g = 1)
+        Dense L(nc, nc), M(nc, nc);
+        for (int i = 0; i < nc; ++i)
+            for (int j = 0; j < nc; ++j) {
+                L(i, j) = g.Lc(base + i, base + j);
+                M(i, j) = g.Mc(base + i, base + j);
+            }
+        std::vector<double> lam;
+        Dense S;
+        generalized_eig(L, M, lam, S);
+        check(L, M, lam, S);
+        for (int i = 0; i < nc; ++i) {
+            t[oLC + i] = lam[i];
+            for (int j = 0; j < nc; ++j) t[oSC + i * nc + j] = S(i, j);
+        }
+        for (int i = 0; i < nd; ++i)
+            for (int j = 0; j < nc; ++j) t[oDP + i * nc + j] = g.D(base + i, base + j);
+    }
+    // discontinuous windows: 4 boundary types
+    {
+        Global1D g4(r, 4, h, penalty_factor), g2(r, 2, h, penalty_factor);
+        const Global1D* src[4] = {&g4, &g4, &g4, &g2};
+        const int base[4] = {m, 0, 2 * m, 0};
+        for (int ty = 0; ty < 4; ++ty) {
+            Dense L(nd, nd), M(nd, nd);
+            for (int i = 0; i < nd; ++i)
+                for (int j = 0; j < nd; ++j) {
+                    L(i, j) = src[ty]->Ld(base[ty] + i, base[ty] + j);
+                    M(i, j) = src[ty]->Md(base[ty] + i, base[ty] + j);
+                }
+            std::vector<double> lam;
+            Dense S;
+            generalized_eig(L, M, lam, S);
+            check(L, M, lam, S);
+            for (int i = 0; i < nd; ++i) {
+                t[oLD + ty * nd + i] = lam[i];
+                for (int j = 0; j < nd; ++j) t[oSD + ty * nd * nd + i * nd + j] = S(i, j);
+            }
+        }
+    }
+    for (int i = 0; i < nd; ++i) t[oMD + i] = h * r.wg[i % m];
+    return t;
+}
+
+}  // namespace smg

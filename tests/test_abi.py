@@ -39,9 +39,10 @@ def test_create_validates_config_without_gpu():
     L = load_library()
     h = ctypes.c_void_p()
     for bad in [(3, 1, 1), (8, 0, 1), (8, 6, 1), (8, 2, 5), (0, 1, 1)]:
-        cfg = L.Config(*bad, 2.0)
+        cfg = L.Config(*bad, 2.0, 1e-10, 50)
         assert L.lib.stokesmg_create(ctypes.byref(cfg), ctypes.byref(h)) == L.EINVAL
-    cfg = L.Config(16, 3, 5, 2.0)
+    cfg = L.Config(16, 3, 5, 2.0, 1e-10, 50)
+    assert L.lib.stokesmg_create(ctypes.byref(L.Config(16, 3, 5, 1.5, 1e-10, 50)), ctypes.byref(h)) == L.EUNSUPPORTED
     assert L.lib.stokesmg_create(ctypes.byref(cfg), ctypes.byref(h)) == L.OK
     assert L.lib.stokesmg_num_levels(h) == 5
     a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
