@@ -131,6 +131,51 @@ int patch_smooth(stokesmg_t* h, int level, int dtype, void* x, const void* b, in
  * `stream`. */
 int stokesmg_cg_stats(stokesmg_t* h, int64_t* iterations, int64_t* solves, int reset, void* stream);
 
+/* x = P_L^{-1} b: one V-cycle (Sec. 3) from x = 0 on the finest level:
+ * pre-smoothing (one patch_smooth sweep), coarse-grid correction with
+ * restriction P^T, recursion, prolongation P (the canonical embedding of the
+ * coarse space), post-smoothing (one sweep); on the coarsest level the dense
+ * pseudo-inverse of K_0 (FP64 matrix also inside an FP32 cycle).  dtype F64
+ * or F32 for b and x (finest-level vectors).  Requires degree <= 3 and a
+ * coarsest level with at most 1000 unknowns (EUNSUPPORTED otherwise). */
+int vcycle(stokesmg_t* h, int dtype, const void* b, void* x, void* stream);
+
+#define STOKESMG_MAX_HISTORY 512
+typedef struct {
+    int    iterations;        /* FGMRES steps (V-cycle applications) */
+    int    converged;         /* relative residual estimate reached rtol */
+    double rel_residual;      /* ||b - K x|| / ||b|| of the returned x, recomputed in FP64 */
+    double nu;                /* fractional iteration count -8 / log10(rbar) (Sec. 3.3) */
+    double history[STOKESMG_MAX_HISTORY];   /* residual estimate / ||b|| after each step; [0] = 1 */
+    long long cg_iterations;  /* local Schur CG iterations during the solve */
+    long long local_solves;   /* local patch solves during the solve */
+    double seconds;           /* wall time of the solve call */
+} stokesmg_info;
+
+/* Bytes of the caller-owned solve workspace for FGMRES(restart), 1 <= restart <= 60:
+ * (2 restart + 4) FP64 vectors of the finest level. */
+int stokesmg_solve_workspace_size(const stokesmg_t* h, int restart, size_t* bytes);
+
+/* Solves K x = b on the finest level by right-preconditioned restarted FGMRES
+ * (GMRES preconditioned by the V-cycle, Sec. 3.3), x_0 = 0, until the
+ * Euclidean residual estimate satisfies ||r|| <= rtol ||b|| or max_it steps.
+ * The outer loop is FP64; vcycle_dtype F32 runs the whole V-cycle in FP32 and
+ * converts at its entry and exit (Sec. 4.3).  b and x are FP64 device vectors;
+ * the returned pressure has zero integral mean.  Synchronizes `stream` a few
+ * times per step (Hessenberg scalars).  ENOTCONV when max_it is reached (info
+ * and x are still filled).  info may be NULL. */
+int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, int restart, int vcycle_dtype,
+          void* solve_ws, size_t solve_ws_bytes, stokesmg_info* info, void* stream);
+
+/* Right-hand side of a manufactured problem on level `level` (FP64 device
+ * vector): (f, phi) + the boundary terms 2 gamma <g, phi> - <g, d_n phi> of
+ * Eq. bilinear for the tangential data g = u, by Gauss quadrature with k+2
+ * points per direction; pressure rows zero.
+ * STOKESMG_PROBLEM_SINE: u = curl(sin(pi x) sin(pi y) sin(pi z) (1,1,1)),
+ * p = cos(pi x) cos(pi y) cos(pi z), f = -Laplace u + grad p. */
+#define STOKESMG_PROBLEM_SINE 0
+int stokesmg_rhs_manufactured(stokesmg_t* h, int level, int problem, double* b, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,12 +87,19 @@ class Multigrid:
         assert self.levels[-1]["S"].n == n_fine, "n_fine must be n_coarse * 2^L"
         self.P = [None] + [prolongation(self.levels[l - 1]["S"], self.levels[l]["S"])
                            for l in range(1, len(self.levels))]
-        K0 = self.levels[0]["K"].toarray()
-        lam, Q = np.linalg.eigh(K0)
-        drop = np.argmin(np.abs(lam))
-        keep = np.ones(len(lam), dtype=bool)
-        keep[drop] = False
-        self.K0_pinv = (Q[:, keep] / lam[keep]) @ Q[:, keep].T
+        self._K0_pinv = None
+
+    @property
+    def K0_pinv(self):
+        """Dense pseudo-inverse of the coarsest matrix (computed on first use)."""
+        if self._K0_pinv is None:
+            K0 = self.levels[0]["K"].toarray()
+            lam, Q = np.linalg.eigh(K0)
+            drop = np.argmin(np.abs(lam))
+            keep = np.ones(len(lam), dtype=bool)
+            keep[drop] = False
+            self._K0_pinv = (Q[:, keep] / lam[keep]) @ Q[:, keep].T
+        return self._K0_pinv
 
     @property
     def fine(self):

@@ -134,3 +134,45 @@ class StokesMG:
         self._check(_lib.lib.stokesmg_cg_stats(self._h, ctypes.byref(a), ctypes.byref(b), int(reset),
                                                self._stream()))
         return a.value, b.value
+
+    def vcycle(self, b, x=None):
+        """x = P^{-1} b: one V-cycle on the finest level (dtype of b)."""
+        if x is None:
+            x = _torch().empty_like(b)
+        self._vec(b, -1, "b")
+        self._vec(x, -1, "x")
+        self._check(_lib.lib.vcycle(self._h, self._dtype_code(b), b.data_ptr(), x.data_ptr(), self._stream()))
+        return x
+
+    def rhs_manufactured(self, level=-1, problem=0):
+        """Right-hand side of a manufactured problem (0: the sine/curl solution), FP64."""
+        torch = _torch()
+        level = level % self.n_levels
+        b = torch.empty(self.ndof(level), dtype=torch.float64, device=self.device)
+        self._check(_lib.lib.stokesmg_rhs_manufactured(self._h, level, problem, b.data_ptr(), self._stream()))
+        return b
+
+    def solve(self, b, rtol=1e-8, max_it=100, restart=30, vcycle_dtype="f64", x=None, allow_notconv=False):
+        """FGMRES(restart) preconditioned by the V-cycle; returns (x, info dict)."""
+        torch = _torch()
+        if b.dtype != torch.float64:
+            raise TypeError("b must be float64")
+        self._vec(b, -1, "b")
+        if x is None:
+            x = torch.empty_like(b)
+        nb = ctypes.c_size_t()
+        self._check(_lib.lib.stokesmg_solve_workspace_size(self._h, restart, ctypes.byref(nb)))
+        ws = getattr(self, "_solve_ws", None)
+        if ws is None or ws.numel() < nb.value:
+            self._solve_ws = None
+            ws = self._solve_ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        info = _lib.Info()
+        vd = F64 if vcycle_dtype == "f64" else F32
+        rc = _lib.lib.solve(self._h, b.data_ptr(), x.data_ptr(), rtol, max_it, restart, vd, ws.data_ptr(),
+                            ws.numel(), ctypes.byref(info), self._stream())
+        if rc != 0 and not (allow_notconv and rc == _lib.ENOTCONV):
+            self._check(rc)
+        hist = [info.history[i] for i in range(min(info.iterations + 1, _lib.MAX_HISTORY))]
+        return x, dict(iterations=info.iterations, converged=bool(info.converged), rel_residual=info.rel_residual,
+                       nu=info.nu, history=hist, cg_iterations=info.cg_iterations, local_solves=info.local_solves,
+                       seconds=info.seconds)

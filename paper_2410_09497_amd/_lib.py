@@ -16,6 +16,16 @@ class Config(ctypes.Structure):
                 ("penalty_factor", ctypes.c_double), ("cg_rtol", ctypes.c_double), ("cg_max_it", ctypes.c_int)]
 
 
+MAX_HISTORY = 512
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("nu", ctypes.c_double), ("history", ctypes.c_double * MAX_HISTORY),
+                ("cg_iterations", ctypes.c_longlong), ("local_solves", ctypes.c_longlong),
+                ("seconds", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2410_09497_amd/build.py "
@@ -34,6 +44,10 @@ def _load():
         "stokes_residual": (i32, [vp, i32, i32, vp, vp, vp, vp]),
         "patch_smooth": (i32, [vp, i32, i32, vp, vp, i32, vp]),
         "stokesmg_cg_stats": (i32, [vp, i64p, i64p, i32, vp]),
+        "vcycle": (i32, [vp, i32, vp, vp, vp]),
+        "stokesmg_solve_workspace_size": (i32, [vp, i32, szp]),
+        "solve": (i32, [vp, vp, vp, ctypes.c_double, i32, i32, i32, vp, ctypes.c_size_t, ctypes.POINTER(Info), vp]),
+        "stokesmg_rhs_manufactured": (i32, [vp, i32, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -46,4 +60,5 @@ lib = _load()
 
 EXPORTED = ["stokesmg_create", "stokesmg_destroy", "stokesmg_last_error", "stokesmg_num_levels",
             "stokesmg_sizes", "stokesmg_workspace_size", "stokesmg_set_workspace", "stokes_apply",
-            "stokes_residual", "patch_smooth", "stokesmg_cg_stats"]
+            "stokes_residual", "patch_smooth", "stokesmg_cg_stats", "vcycle", "stokesmg_solve_workspace_size",
+            "solve", "stokesmg_rhs_manufactured"]

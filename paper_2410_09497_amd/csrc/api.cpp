@@ -17,11 +17,6 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-int64_t level_total(const stokesmg* h, int level) {
-    const int64_t N1 = h->lv[level].N1;
-    return 3 * (N1 - 1) * N1 * N1 + N1 * N1 * N1;
-}
-
 int check_level_dtype(stokesmg* h, int level, int dtype) {
     if (level < 0 || level >= h->n_levels) return h->fail(STOKESMG_EINVAL, "level out of range");
     if (dtype != STOKESMG_F64 && dtype != STOKESMG_F32) return h->fail(STOKESMG_EINVAL, "dtype must be F64 or F32");
@@ -59,6 +54,11 @@ int stokesmg_create(const stokesmg_config* cfg, stokesmg_t** out) {
             h->lv.push_back(smg::build_level_tables(ref, nl, cfg->penalty_factor));
             h->lv.back().patch = smg::build_patch_tables(ref, nl, cfg->penalty_factor);
         }
+        h->tr.resize(L);
+        for (int l = 1; l < L; ++l) h->tr[l] = smg::build_transfer(ref, n >> (L - l));
+        const int n0 = n >> (L - 1);
+        const int64_t N0 = level_total(h, 0);
+        if (N0 <= 1000) h->coarse_pinv = smg::coarse_pseudo_inverse(ref, n0, cfg->penalty_factor, &h->N0);
     } catch (const std::exception& e) {
         delete h;
         return STOKESMG_EINVAL;
@@ -79,6 +79,34 @@ int stokesmg_create(const stokesmg_config* cfg, stokesmg_t** out) {
     off = align256(off + 2 * sizeof(int));
     h->r_vec = off;
     off = align256(off + size_t(level_total(h, L - 1)) * sizeof(double));
+    h->tro.resize(L);
+    for (int l = 1; l < L; ++l) {
+        auto& T = h->tr[l];
+        auto& o = h->tro[l];
+        auto put = [&](const smg::Rows1D& R, size_t& oi, size_t& ow, int& w) {
+            oi = off;
+            off = align256(off + R.idx.size() * sizeof(int));
+            ow = off;
+            off = align256(off + R.w.size() * sizeof(double));
+            w = R.width;
+        };
+        put(T.pd, o.pd_i, o.pd_w, o.wpd);
+        put(T.pc, o.pc_i, o.pc_w, o.wpc);
+        put(T.rd, o.rd_i, o.rd_w, o.wrd);
+        put(T.rc, o.rc_i, o.rc_w, o.wrc);
+    }
+    h->coarse_off = off;
+    off = align256(off + h->coarse_pinv.size() * sizeof(double));
+    for (int l = 0; l + 1 < L; ++l) {
+        h->xl.push_back(off);
+        off = align256(off + size_t(level_total(h, l)) * sizeof(double));
+        h->bl.push_back(off);
+        off = align256(off + size_t(level_total(h, l)) * sizeof(double));
+    }
+    h->wg_off = off;
+    off = align256(off + (k + 1) * sizeof(double));
+    h->scratch_off = off;
+    off = align256(off + size_t(stokesmg::kScratch) * sizeof(double));
     h->ws_needed = off;
     *out = h;
     return STOKESMG_OK;
@@ -126,6 +154,27 @@ int stokesmg_set_workspace(stokesmg_t* h, void* dev_ptr, size_t bytes, void* str
         if (int rc = upload(h->lv[l].stencil, h->tab_f64[l], h->tab_f32[l])) return rc;
         if (int rc = upload(h->lv[l].patch, h->ptab_f64[l], h->ptab_f32[l])) return rc;
     }
+    for (int l = 1; l < h->n_levels; ++l) {
+        const auto& T = h->tr[l];
+        const auto& o = h->tro[l];
+        const smg::Rows1D* R[4] = {&T.pd, &T.pc, &T.rd, &T.rc};
+        const size_t oi[4] = {o.pd_i, o.pc_i, o.rd_i, o.rc_i}, ow[4] = {o.pd_w, o.pc_w, o.rd_w, o.rc_w};
+        for (int q = 0; q < 4; ++q) {
+            SMG_HIP(h, hipMemcpyAsync(h->ws + oi[q], R[q]->idx.data(), R[q]->idx.size() * sizeof(int),
+                                      hipMemcpyHostToDevice, st));
+            SMG_HIP(h, hipMemcpyAsync(h->ws + ow[q], R[q]->w.data(), R[q]->w.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, st));
+        }
+    }
+    if (!h->coarse_pinv.empty())
+        SMG_HIP(h, hipMemcpyAsync(h->ws + h->coarse_off, h->coarse_pinv.data(), h->coarse_pinv.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, st));
+    {
+        smg::Ref1D ref(h->cfg.k);
+        SMG_HIP(h, hipMemcpyAsync(h->ws + h->wg_off, ref.wg.data(), ref.wg.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, st));
+        SMG_HIP(h, hipStreamSynchronize(st));
+    }
     SMG_HIP(h, hipMemsetAsync(h->ws + h->cg_counter, 0, 2 * sizeof(int), st));
     SMG_HIP(h, hipStreamSynchronize(st));
     return STOKESMG_OK;
@@ -166,7 +215,8 @@ int patch_smooth(stokesmg_t* h, int level, int dtype, void* x, const void* b, in
     if (h->cfg.k > 3) return h->fail(STOKESMG_EUNSUPPORTED, "patch_smooth is built for degrees 1..3");
     const size_t es = dtype == STOKESMG_F64 ? 8 : 4;
     const size_t bytes = size_t(level_total(h, level)) * es;
-    if (overlap(x, b, bytes) || overlap(x, h->ws, h->ws_bytes) || overlap(b, h->ws, h->ws_bytes))
+    if (overlap(x, b, bytes) || ranges_overlap(x, bytes, h->ws, h->ws_bytes) ||
+        ranges_overlap(b, bytes, h->ws, h->ws_bytes))
         return h->fail(STOKESMG_EINVAL, "x, b and the workspace must not overlap");
     const bool f64 = dtype == STOKESMG_F64;
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -3,10 +3,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <string>
 #include <vector>
 
 #include "../../include/stokesmg.h"
+#include "mg_tables.hpp"
 #include "tables.hpp"
 
 struct stokesmg {
@@ -25,11 +27,39 @@ struct stokesmg {
     size_t cg_counter = 0;                   // two int counters: CG iterations, patch solves
     size_t ws_needed = 0;
 
+    // multigrid: transfers between level l-1 and l (index l >= 1), coarse pseudo-inverse,
+    // vectors x_l, b_l of the levels below the finest (8 B per unknown, either dtype)
+    struct TransferOff {
+        size_t pd_i, pd_w, pc_i, pc_w, rd_i, rd_w, rc_i, rc_w;
+        int wpd, wpc, wrd, wrc;
+    };
+    std::vector<smg::Transfer1D> tr;          // host copies (index l >= 1)
+    std::vector<TransferOff> tro;
+    std::vector<double> coarse_pinv;          // empty if the coarsest level is too large
+    int N0 = 0;
+    size_t coarse_off = 0;
+    std::vector<size_t> xl, bl;               // per level l < L-1
+    size_t wg_off = 0;                        // Gauss weights (k+1 doubles)
+    size_t scratch_off = 0;                   // reductions: kScratch doubles
+    // scratch regions (in doubles): coefficients / dot results, pressure moment, multi-dot partials
+    static constexpr int kCoef = 0, kMoment = 64, kPartial = 2048, kPartialBlocks = 1024;
+    static constexpr int kScratch = kPartial + kPartialBlocks * 64;
+
     int fail(int code, const std::string& msg) {
         err = msg;
         return code;
     }
 };
+
+inline int64_t level_total(const stokesmg* h, int level) {
+    const int64_t N1 = h->lv[level].N1;
+    return 3 * (N1 - 1) * N1 * N1 + N1 * N1 * N1;
+}
+
+inline bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return pa < pb + nb && pb < pa + na;
+}
 
 #define SMG_HIP(h, call)                                                                     \
     do {                                                                                     \

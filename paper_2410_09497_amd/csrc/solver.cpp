@@ -1,0 +1,361 @@
+// V-cycle (Sec. 3), FGMRES around it (Sec. 3.3) and the separable
+// right-hand-side assembly of the manufactured problems.  Host orchestration;
+// every vector operation is a device kernel.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "apply.hpp"
+#include "handle.hpp"
+#include "mg_kernels.hpp"
+#include "patch.hpp"
+
+namespace {
+
+using smg::Rows1D;
+
+int vcycle_level(stokesmg* h, int l, bool f64, const void* b, void* x, hipStream_t st) {
+    if (l == 0) {
+        if (h->coarse_pinv.empty()) return h->fail(STOKESMG_EUNSUPPORTED, "coarsest level too large for the dense solve");
+        SMG_HIP(h, smg::launch_coarse_gemv(f64, reinterpret_cast<const double*>(h->ws + h->coarse_off), b, x, h->N0, st));
+        return STOKESMG_OK;
+    }
+    const int n = h->lv[l].n, k = h->cfg.k;
+    const size_t N = size_t(level_total(h, l));
+    const void* tab = h->ws + (f64 ? h->tab_f64[l] : h->tab_f32[l]);
+    const void* ptab = h->ws + (f64 ? h->ptab_f64[l] : h->ptab_f32[l]);
+    void* r = h->ws + h->r_vec;
+    int* counters = reinterpret_cast<int*>(h->ws + h->cg_counter);
+    auto sweep = [&]() -> int {
+        for (int c = 0; c < 8; ++c) {
+            SMG_HIP(h, smg::launch_apply(k, f64, true, x, b, r, tab, n, st));
+            SMG_HIP(h, smg::launch_patch_solve(k, f64, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters, st));
+        }
+        return STOKESMG_OK;
+    };
+    // pre-smoothing from x = 0
+    SMG_HIP(h, smg::launch_zero(f64, x, N, st));
+    if (int rc = sweep()) return rc;
+    // coarse-grid correction: b_{l-1} = P^T (b - K x), x += P P_{l-1}^{-1} b_{l-1}
+    SMG_HIP(h, smg::launch_apply(k, f64, true, x, b, r, tab, n, st));
+    const auto& o = h->tro[l];
+    char* w = h->ws;
+    void* bc = w + h->bl[l - 1];
+    void* xc = w + h->xl[l - 1];
+    const int N1f = h->lv[l].N1, N1c = h->lv[l - 1].N1;
+    SMG_HIP(h, smg::launch_transfer(f64, false, r, bc, N1c, N1f, reinterpret_cast<const int*>(w + o.rd_i),
+                                    reinterpret_cast<const double*>(w + o.rd_w), o.wrd,
+                                    reinterpret_cast<const int*>(w + o.rc_i),
+                                    reinterpret_cast<const double*>(w + o.rc_w), o.wrc, st));
+    if (int rc = vcycle_level(h, l - 1, f64, bc, xc, st)) return rc;
+    SMG_HIP(h, smg::launch_transfer(f64, true, xc, x, N1f, N1c, reinterpret_cast<const int*>(w + o.pd_i),
+                                    reinterpret_cast<const double*>(w + o.pd_w), o.wpd,
+                                    reinterpret_cast<const int*>(w + o.pc_i),
+                                    reinterpret_cast<const double*>(w + o.pc_w), o.wpc, st));
+    // post-smoothing
+    return sweep();
+}
+
+int check_mg(stokesmg* h) {
+    if (!h->ws) return h->fail(STOKESMG_ENOMEM, "no workspace set");
+    if (h->cfg.k > 3) return h->fail(STOKESMG_EUNSUPPORTED, "the patch smoother is built for degrees 1..3");
+    for (int l = 1; l < h->n_levels; ++l)
+        if (h->lv[l].n < 2) return h->fail(STOKESMG_EINVAL, "level without interior vertices");
+    if (h->coarse_pinv.empty()) return h->fail(STOKESMG_EUNSUPPORTED, "coarsest level too large for the dense solve");
+    return STOKESMG_OK;
+}
+
+// out[0..nv) = V_j . w on the host (one synchronization)
+int host_dots(stokesmg* h, const double* V, size_t ld, const double* w, int nv, size_t n, double* out,
+              hipStream_t st) {
+    double* scr = reinterpret_cast<double*>(h->ws + h->scratch_off);
+    const int nblocks = stokesmg::kPartialBlocks;
+    double* partial = scr + stokesmg::kPartial;
+    double* res = scr + stokesmg::kCoef;   // nv <= 61
+    SMG_HIP(h, smg::launch_multidot(V, ld, w, nv, n, partial, nblocks, res, st));
+    SMG_HIP(h, hipMemcpyAsync(out, res, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+    SMG_HIP(h, hipStreamSynchronize(st));
+    return STOKESMG_OK;
+}
+
+// ------------------------------------------------ separable right-hand sides
+// 1D factor functions of the manufactured problems
+enum Fn { ONE, SINPI, COSPI };
+double fn(int f, double x) {
+    switch (f) {
+        case SINPI: return std::sin(M_PI * x);
+        case COSPI: return std::cos(M_PI * x);
+        default: return 1.0;
+    }
+}
+struct Term {       // coef * g0(x) g1(y) g2(z)
+    double c;
+    int g[3];
+};
+
+// 1D load vectors of function g against the basis of one direction kind on n cells:
+// value[position] = int g phi_position (Gauss with k+2 points per cell), and the
+// boundary vector bnd[position] = sum over the two ends s of g(s) (2 gamma phi(s) - n_s phi'(s))
+void load_1d(const smg::Ref1D& r, int n, bool cont, int g, double gamma, std::vector<double>& val,
+             std::vector<double>& bnd) {
+    const int k = r.k, m = k + 1, N1 = n * m;
+    const double h = 1.0 / n;
+    std::vector<double> xq, wq;
+    smg::gauss_rule(k + 2, xq, wq);
+    if (!cont) {
+        val.assign(N1, 0.0);
+        bnd.assign(N1, 0.0);
+        for (int c = 0; c < n; ++c)
+            for (int a = 0; a < m; ++a) {
+                double s = 0.0;
+                for (size_t q = 0; q < xq.size(); ++q) s += wq[q] * h * fn(g, (c + xq[q]) * h) * smg::lagrange(r.xg, a, xq[q]);
+                val[c * m + a] = s;
+            }
+        for (int a = 0; a < m; ++a) {
+            bnd[a] += fn(g, 0.0) * (2.0 * gamma * r.eL[a] + r.dL[a] / h);                // n = -1: -n phi' = +phi'
+            bnd[(n - 1) * m + a] += fn(g, 1.0) * (2.0 * gamma * r.eR[a] - r.dR[a] / h);
+        }
+    } else {
+        std::vector<double> full(N1 + 1, 0.0), fb(N1 + 1, 0.0);
+        for (int c = 0; c < n; ++c)
+            for (int b = 0; b <= m; ++b) {
+                double s = 0.0;
+                for (size_t q = 0; q < xq.size(); ++q) s += wq[q] * h * fn(g, (c + xq[q]) * h) * smg::lagrange(r.xl, b, xq[q]);
+                full[c * m + b] += s;
+            }
+        val.assign(full.begin() + 1, full.end() - 1);   // interior nodes only
+        bnd.assign(N1 - 1, 0.0);   // the boundary nodes of the continuous basis are eliminated
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int vcycle(stokesmg_t* h, int dtype, const void* b, void* x, void* stream) {
+    if (!h) return STOKESMG_EINVAL;
+    if (dtype != STOKESMG_F64 && dtype != STOKESMG_F32) return h->fail(STOKESMG_EINVAL, "dtype must be F64 or F32");
+    if (int rc = check_mg(h)) return rc;
+    if (!b || !x) return h->fail(STOKESMG_EINVAL, "null vector");
+    const int L = h->n_levels - 1;
+    const size_t bytes = size_t(level_total(h, L)) * (dtype == STOKESMG_F64 ? 8 : 4);
+    if (ranges_overlap(b, bytes, x, bytes) || ranges_overlap(x, bytes, h->ws, h->ws_bytes) ||
+        ranges_overlap(b, bytes, h->ws, h->ws_bytes))
+        return h->fail(STOKESMG_EINVAL, "b, x and the workspace must not overlap");
+    return vcycle_level(h, L, dtype == STOKESMG_F64, b, x, static_cast<hipStream_t>(stream));
+}
+
+int stokesmg_solve_workspace_size(const stokesmg_t* h, int restart, size_t* bytes) {
+    if (!h || !bytes || restart < 1 || restart > 60) return STOKESMG_EINVAL;
+    const size_t N = size_t(level_total(h, h->n_levels - 1));
+    // V: restart+1, Z: restart, w, V-cycle input and output: FP64 each
+    *bytes = (size_t(2 * restart + 4) * N) * sizeof(double) + 256;
+    return STOKESMG_OK;
+}
+
+int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, int restart, int vcycle_dtype,
+          void* solve_ws, size_t solve_ws_bytes, stokesmg_info* info, void* stream) {
+    if (!h) return STOKESMG_EINVAL;
+    if (int rc = check_mg(h)) return rc;
+    if (!b || !x || !solve_ws || !(rtol > 0) || max_it < 1 || restart < 1 || restart > 60)
+        return h->fail(STOKESMG_EINVAL, "bad solve arguments");
+    if (vcycle_dtype != STOKESMG_F64 && vcycle_dtype != STOKESMG_F32)
+        return h->fail(STOKESMG_EINVAL, "vcycle dtype must be F64 or F32");
+    size_t need = 0;
+    stokesmg_solve_workspace_size(h, restart, &need);
+    if (solve_ws_bytes < need) return h->fail(STOKESMG_ENOMEM, "solve workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    const int L = h->n_levels - 1;
+    const int k = h->cfg.k, n = h->lv[L].n;
+    const size_t N = size_t(level_total(h, L));
+    const size_t nb = N * sizeof(double);
+    if (ranges_overlap(b, nb, x, nb) || ranges_overlap(x, nb, solve_ws, solve_ws_bytes) ||
+        ranges_overlap(b, nb, solve_ws, solve_ws_bytes) || ranges_overlap(x, nb, h->ws, h->ws_bytes))
+        return h->fail(STOKESMG_EINVAL, "b, x and the workspaces must not overlap");
+    double* base = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(solve_ws) + 255) & ~uintptr_t(255));
+    double* V = base;                              // restart + 1 vectors
+    double* Z = V + size_t(restart + 1) * N;       // restart vectors
+    double* w = Z + size_t(restart) * N;
+    double* vin = w + N;                           // V-cycle input / output in its dtype
+    double* vout = vin + N;
+    const bool f32 = vcycle_dtype == STOKESMG_F32;
+    const void* tab64 = h->ws + h->tab_f64[L];
+    double* coef = reinterpret_cast<double*>(h->ws + h->scratch_off);   // device coefficients (<= 64)
+    if (info) std::memset(info, 0, sizeof(*info));
+    int64_t it0 = 0, so0 = 0;
+    {
+        int c[2];
+        SMG_HIP(h, hipMemcpyAsync(c, h->ws + h->cg_counter, sizeof(c), hipMemcpyDeviceToHost, st));
+        SMG_HIP(h, hipStreamSynchronize(st));
+        it0 = c[0];
+        so0 = c[1];
+    }
+
+    double bnorm = 0.0;
+    if (int rc = host_dots(h, b, 0, b, 1, N, &bnorm, st)) return rc;
+    bnorm = std::sqrt(bnorm);
+    SMG_HIP(h, smg::launch_zero(true, x, N, st));
+    std::vector<double> hist{1.0};
+    int it = 0;
+    bool conv = bnorm == 0.0;
+    std::vector<double> H(size_t(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), hv(restart + 1),
+        h2(restart + 1);
+    while (!conv && it < max_it) {
+        // V_0 = r / |r|
+        SMG_HIP(h, smg::launch_apply(k, true, true, x, b, V, tab64, n, st));
+        double beta = 0.0;
+        if (int rc = host_dots(h, V, 0, V, 1, N, &beta, st)) return rc;
+        beta = std::sqrt(beta);
+        if (beta / bnorm <= rtol) {
+            conv = true;
+            break;
+        }
+        SMG_HIP(h, smg::launch_multiaxpy(V, 0, coef, 0, 0.0, 1.0 / beta, V, N, st));
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jdone = 0;
+        for (int j = 0; j < restart; ++j) {
+            double* vj = V + size_t(j) * N;
+            double* zj = Z + size_t(j) * N;
+            // z_j = P^{-1} v_j (FP32 V-cycle: convert on entry and exit, the precision boundary)
+            if (f32) {
+                SMG_HIP(h, smg::launch_convert(true, vj, vin, N, st));
+                if (int rc = vcycle_level(h, L, false, vin, vout, st)) return rc;
+                SMG_HIP(h, smg::launch_convert(false, vout, zj, N, st));
+            } else {
+                if (int rc = vcycle_level(h, L, true, vj, zj, st)) return rc;
+            }
+            // w = K z_j, orthogonalized twice against V_0..V_j (classical Gram-Schmidt, twice)
+            SMG_HIP(h, smg::launch_apply(k, true, false, zj, nullptr, w, tab64, n, st));
+            if (int rc = host_dots(h, V, N, w, j + 1, N, hv.data(), st)) return rc;
+            SMG_HIP(h, hipMemcpyAsync(coef, hv.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, st));
+            SMG_HIP(h, smg::launch_multiaxpy(V, N, coef, j + 1, -1.0, 1.0, w, N, st));
+            SMG_HIP(h, hipStreamSynchronize(st));
+            if (int rc = host_dots(h, V, N, w, j + 1, N, h2.data(), st)) return rc;
+            SMG_HIP(h, hipMemcpyAsync(coef, h2.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, st));
+            SMG_HIP(h, smg::launch_multiaxpy(V, N, coef, j + 1, -1.0, 1.0, w, N, st));
+            SMG_HIP(h, hipStreamSynchronize(st));
+            for (int i = 0; i <= j; ++i) H[size_t(i) * restart + j] = hv[i] + h2[i];
+            double hn = 0.0;
+            if (int rc = host_dots(h, w, 0, w, 1, N, &hn, st)) return rc;
+            hn = std::sqrt(hn);
+            H[size_t(j + 1) * restart + j] = hn;
+            double* vn = V + size_t(j + 1) * N;
+            SMG_HIP(h, hipMemcpyAsync(vn, w, nb, hipMemcpyDeviceToDevice, st));
+            if (hn > 0) SMG_HIP(h, smg::launch_multiaxpy(V, 0, coef, 0, 0.0, 1.0 / hn, vn, N, st));
+            // Givens rotations
+            for (int i = 0; i < j; ++i) {
+                const double a = H[size_t(i) * restart + j], bb = H[size_t(i + 1) * restart + j];
+                H[size_t(i) * restart + j] = cs[i] * a + sn[i] * bb;
+                H[size_t(i + 1) * restart + j] = -sn[i] * a + cs[i] * bb;
+            }
+            const double a = H[size_t(j) * restart + j], bb = H[size_t(j + 1) * restart + j];
+            const double den = std::hypot(a, bb);
+            cs[j] = a / den;
+            sn[j] = bb / den;
+            H[size_t(j) * restart + j] = den;
+            H[size_t(j + 1) * restart + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            jdone = j + 1;
+            hist.push_back(std::fabs(g[j + 1]) / bnorm);
+            if (hist.back() <= rtol || it >= max_it) break;
+        }
+        // x += Z y, H(0:j, 0:j) y = g(0:j)
+        std::vector<double> y(jdone);
+        for (int i = jdone - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int q = i + 1; q < jdone; ++q) s -= H[size_t(i) * restart + q] * y[q];
+            y[i] = s / H[size_t(i) * restart + i];
+        }
+        SMG_HIP(h, hipMemcpyAsync(coef, y.data(), jdone * sizeof(double), hipMemcpyHostToDevice, st));
+        SMG_HIP(h, smg::launch_multiaxpy(Z, N, coef, jdone, 1.0, 1.0, x, N, st));
+        SMG_HIP(h, hipStreamSynchronize(st));
+        if (hist.back() <= rtol) conv = true;
+    }
+    // zero-mean pressure (L^2_0), then the true residual of the returned x
+    SMG_HIP(h, smg::launch_normalize_pressure(true, x, h->lv[L].N1, k + 1,
+                                              reinterpret_cast<const double*>(h->ws + h->wg_off), h->lv[L].h,
+                                              reinterpret_cast<double*>(h->ws + h->scratch_off) + stokesmg::kMoment, st));
+    SMG_HIP(h, smg::launch_apply(k, true, true, x, b, w, tab64, n, st));
+    double rn = 0.0;
+    if (int rc = host_dots(h, w, 0, w, 1, N, &rn, st)) return rc;
+    const auto t1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->iterations = it;
+        info->converged = conv ? 1 : 0;
+        info->rel_residual = bnorm > 0 ? std::sqrt(rn) / bnorm : 0.0;
+        const double last = hist.back();
+        info->nu = (it > 0 && last > 0) ? -8.0 / (std::log10(last) / it) : 0.0;
+        for (size_t i = 0; i < hist.size() && i < STOKESMG_MAX_HISTORY; ++i) info->history[i] = hist[i];
+        int c[2];
+        SMG_HIP(h, hipMemcpyAsync(c, h->ws + h->cg_counter, sizeof(c), hipMemcpyDeviceToHost, st));
+        SMG_HIP(h, hipStreamSynchronize(st));
+        info->cg_iterations = c[0] - it0;
+        info->local_solves = c[1] - so0;
+        info->seconds = std::chrono::duration<double>(t1 - t0).count();
+    }
+    return conv ? STOKESMG_OK : h->fail(STOKESMG_ENOTCONV, "FGMRES reached max_it");
+}
+
+int stokesmg_rhs_manufactured(stokesmg_t* h, int level, int problem, double* b, void* stream) {
+    if (!h) return STOKESMG_EINVAL;
+    if (level < 0 || level >= h->n_levels || !b) return h->fail(STOKESMG_EINVAL, "bad level or null vector");
+    if (problem != STOKESMG_PROBLEM_SINE) return h->fail(STOKESMG_EINVAL, "unknown problem");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const auto& lv = h->lv[level];
+    const int n = lv.n, N1 = lv.N1;
+    smg::Ref1D ref(h->cfg.k);
+    const double P = M_PI, P3 = 3.0 * P * P * P;
+    // f = 3 pi^2 u + grad p and the tangential trace g = u (curl of psi (1,1,1), p = cos cos cos)
+    const std::vector<Term> f[3] = {
+        {{P3, {SINPI, COSPI, SINPI}}, {-P3, {SINPI, SINPI, COSPI}}, {-P, {SINPI, COSPI, COSPI}}},
+        {{P3, {SINPI, SINPI, COSPI}}, {-P3, {COSPI, SINPI, SINPI}}, {-P, {COSPI, SINPI, COSPI}}},
+        {{P3, {COSPI, SINPI, SINPI}}, {-P3, {SINPI, COSPI, SINPI}}, {-P, {COSPI, COSPI, SINPI}}}};
+    const std::vector<Term> u[3] = {{{P, {SINPI, COSPI, SINPI}}, {-P, {SINPI, SINPI, COSPI}}},
+                                    {{P, {SINPI, SINPI, COSPI}}, {-P, {COSPI, SINPI, SINPI}}},
+                                    {{P, {COSPI, SINPI, SINPI}}, {-P, {SINPI, COSPI, SINPI}}}};
+    std::vector<double> out(size_t(level_total(h, level)), 0.0);
+    const size_t nc = size_t(N1 - 1) * N1 * N1;
+    for (int c = 0; c < 3; ++c) {
+        const int ext[3] = {c == 0 ? N1 - 1 : N1, c == 1 ? N1 - 1 : N1, c == 2 ? N1 - 1 : N1};
+        auto add = [&](double coef, const std::vector<double>& a0, const std::vector<double>& a1,
+                       const std::vector<double>& a2) {
+            for (int Zi = 0; Zi < ext[2]; ++Zi)
+                for (int Yi = 0; Yi < ext[1]; ++Yi) {
+                    const double s = coef * a1[Yi] * a2[Zi];
+                    if (s == 0.0) continue;
+                    double* row = out.data() + size_t(c) * nc + size_t(ext[0]) * (Yi + size_t(ext[1]) * Zi);
+                    for (int Xi = 0; Xi < ext[0]; ++Xi) row[Xi] += s * a0[Xi];
+                }
+        };
+        for (const auto& t : f[c]) {
+            std::vector<double> v[3], bd[3];
+            for (int d = 0; d < 3; ++d) load_1d(ref, n, d == c, t.g[d], lv.gamma, v[d], bd[d]);
+            add(t.c, v[0], v[1], v[2]);
+        }
+        // boundary (Nitsche) terms of the tangential data: faces normal to d != c
+        for (const auto& t : u[c]) {
+            std::vector<double> v[3], bd[3];
+            for (int d = 0; d < 3; ++d) load_1d(ref, n, d == c, t.g[d], lv.gamma, v[d], bd[d]);
+            for (int d = 0; d < 3; ++d) {
+                if (d == c) continue;
+                // face integral: the other two directions by quadrature, direction d by the end values
+                std::vector<double> a[3] = {v[0], v[1], v[2]};
+                a[d] = bd[d];
+                add(t.c, a[0], a[1], a[2]);
+            }
+        }
+    }
+    SMG_HIP(h, hipMemcpyAsync(b, out.data(), out.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    SMG_HIP(h, hipStreamSynchronize(st));
+    return STOKESMG_OK;
+}
+
+}  // extern "C"
