@@ -150,6 +150,7 @@ typedef struct {
     long long cg_iterations;  /* local Schur CG iterations during the solve */
     long long local_solves;   /* local patch solves during the solve */
     double seconds;           /* wall time of the solve call */
+    int    fallback_iteration;/* FGMRES step after which the learned solver was replaced (-1: never) */
 } stokesmg_info;
 
 /* Bytes of the caller-owned solve workspace for FGMRES(restart), 1 <= restart <= 60:
@@ -175,6 +176,94 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
  * p = cos(pi x) cos(pi y) cos(pi z), f = -Laplace u + grad p. */
 #define STOKESMG_PROBLEM_SINE 0
 int stokesmg_rhs_manufactured(stokesmg_t* h, int level, int problem, double* b, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned local solver (an extension; the paper's local solvers are exact).
+ *
+ * One network per degree, shared by every interior patch of every level: a
+ * patch whose 8 cells touch no boundary face (vertex v with 2 <= v_d <= n-2)
+ * has, after scaling, the same local problem on every level (A_j ~ h,
+ * B_j ~ h^2 for the separable forms of Sec. 2.2).  Patch-local vectors follow
+ * X_j of Sec. 3.1: [U_x | U_y | U_z | P], each the box of that component's
+ * index grid starting at (v_d - 1)(k+1), 2k+1 entries in the component's own
+ * direction and 2k+2 in the others (and for P), lexicographic with x fastest;
+ * d = 3 (2k+1)(2k+2)^2 + (2k+2)^3 entries.
+ * Normalized pair: input x = (F/h, G/h^2) / s with s = ||(F/h, G/h^2)||_2 of
+ * the patch residual (F, G) = R_j r, target t = (U, h P) / s of the exact
+ * correction (U, P) = K_j^+ (F, G) (Sec. 3.1); a zero residual gives x = t = 0.
+ * Network: y = GELU(GELU(x W1 + b1) W2 + b2) W3 + b3, hidden width 256,
+ * GELU(z) = z Phi(z) with the normal CDF Phi; row-major weights [in x out].
+ * Parameter vector (FP32, P = mlp_num_params): W1 | b1 | W2 | b2 | W3 | b3.
+ * Products run on the matrix cores with FP32 accumulation; mode
+ * STOKESMG_MLP_BF16 rounds the operands to BF16 (production),
+ * STOKESMG_MLP_F32 keeps them in FP32 (checks).
+ * Memory: an MLP workspace (device, caller-owned, 256-byte aligned) sized by
+ * mlp_workspace_size() holds the parameters, gradients, Adam moments and
+ * the activations of up to max_rows rows; set it with mlp_set_workspace().
+ * ------------------------------------------------------------------------ */
+#define STOKESMG_MLP_HIDDEN 256
+#define STOKESMG_MLP_BF16 0
+#define STOKESMG_MLP_F32  1
+
+#define STOKESMG_LOCAL_EXACT 0   /* Schur complement + fast diagonalization (Sec. 3.2) */
+#define STOKESMG_LOCAL_MLP   1   /* network on interior patches, exact solve on the others */
+
+/* d (network width in and out) and P (parameter count) for the handle's degree. */
+int mlp_dims(const stokesmg_t* h, int64_t* d, int64_t* n_params);
+
+/* Bytes of the MLP workspace for batches of up to max_rows rows (training
+ * batches, or the interior patches of one colour per chunk in the smoother). */
+int mlp_workspace_size(const stokesmg_t* h, int64_t max_rows, size_t* bytes);
+int mlp_set_workspace(stokesmg_t* h, void* dev_ptr, size_t bytes, int64_t max_rows);
+
+/* Parameters drawn from a counter-based generator (SplitMix64): weights
+ * uniform in +-sqrt(3 / fan_in), biases zero; Adam moments and step reset. */
+int mlp_init(stokesmg_t* h, uint64_t seed, void* stream);
+
+/* Checkpoint: state = parameters | Adam first moments | Adam second moments
+ * (3 P floats, device) and the Adam step count. */
+int mlp_get_state(stokesmg_t* h, float* state, int64_t* step, void* stream);
+int mlp_set_state(stokesmg_t* h, const float* state, int64_t step, void* stream);
+
+/* Y = network(X) for n rows (X, Y: device, row-major n x d FP32). */
+int mlp_forward(stokesmg_t* h, int mode, const float* X, float* Y, int64_t n, void* stream);
+
+/* Gradients of the loss mean((network(X) - T)^2) over all n d entries with
+ * respect to the parameter vector: grads (P floats, device), loss (one
+ * float, device).  n <= max_rows. */
+int mlp_backward(stokesmg_t* h, int mode, const float* X, const float* T, int64_t n, float* grads, float* loss,
+                 void* stream);
+
+/* One Adam step (Kingma & Ba: beta1 0.9, beta2 0.999, eps 1e-8) on the
+ * handle's parameters with gradient `grads` (device, P floats). */
+int mlp_adam_step(stokesmg_t* h, const float* grads, float lr, void* stream);
+
+/* Pair capture: one FP64 V-cycle x = P^{-1} b with the exact local solver
+ * (as vcycle()), recording the normalized pair of every interior patch
+ * solved on the finest level (pre- and post-smoothing, all colours) into
+ * rows *n, *n + 1, ... of X and T (device, cap x d FP32); *n is advanced,
+ * pairs beyond cap are dropped.  b, x: FP64 finest-level device vectors. */
+int mlp_collect_pairs(stokesmg_t* h, const double* b, double* x, float* X, float* T, int64_t cap, int64_t* n,
+                      void* stream);
+
+/* Training: `epochs` passes over the n pairs in batches of `batch` rows
+ * (batch <= max_rows; a permutation per epoch from SplitMix64(seed, epoch)),
+ * Adam with cosine decay lr_t = lr (1 + cos(pi t / T)) / 2 over the
+ * T = epochs ceil(n / batch) steps.  loss_hist (host, epochs floats, may be
+ * NULL) receives each epoch's mean batch loss.  Synchronizes once per epoch. */
+int mlp_train(stokesmg_t* h, int mode, const float* X, const float* T, int64_t n, int epochs, int batch, float lr,
+              uint64_t seed, float* loss_hist, void* stream);
+
+/* Local solver used by patch_smooth, vcycle and solve from now on, and the
+ * network's precision.  STOKESMG_LOCAL_MLP needs an MLP workspace. */
+int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode);
+
+/* Fallback of the learned solver inside solve(): with the MLP local solver,
+ * after FGMRES step j (j >= 1) with contraction rho_j = res_j / res_{j-1}, the
+ * rest of the solve uses the exact local solver when rho_j > max(2 rho_ref,
+ * 1e-3) or the residual estimate grew.  rho_ref <= 0 disables the rho test
+ * (growth still triggers). */
+int stokesmg_set_fallback(stokesmg_t* h, double rho_ref);
 
 #ifdef __cplusplus
 }

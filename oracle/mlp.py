@@ -84,3 +84,42 @@ def normalize_pair(F, G, U, P, h):
 def denormalize(y, s, nvel, h):
     """Correction (U, P) from a network output for input scale s."""
     return s * y[:nvel], s * y[nvel:] / h
+
+
+def is_interior(Pt, v):
+    """A patch whose 8 cells touch no boundary face (2 <= v_d <= n-2)."""
+    return all(t == (0, 0) for t in Pt.patch_type(v))
+
+
+def learned_local(mg, params):
+    """Local-solver callback for Multigrid.smooth: the network on interior
+    patches (scaled as in the module doc), the pseudo-inverse elsewhere."""
+    def local(l, v, rj):
+        lev = mg.levels[l]
+        S, Pt = lev["S"], lev["patches"]
+        if not is_interior(Pt, v):
+            return Pt.local_solve(lev["K"], v, rj)
+        nv = 3 * Pt.nvel
+        x, _, s = normalize_pair(rj[:nv], rj[nv:], np.zeros(nv), np.zeros(Pt.npres), S.h)
+        if s == 0:
+            return np.zeros_like(rj)
+        y, _ = forward(params, x[None, :])
+        U, P = denormalize(y[0], s, nv, S.h)
+        return np.concatenate([U, P])
+    return local
+
+
+def capture_local(mg, sink, level):
+    """Local-solver callback that solves exactly (pseudo-inverse) and appends
+    the normalized (input, target) pair of every interior patch of `level`
+    to sink (a list), in the order the smoother visits them."""
+    def local(l, v, rj):
+        lev = mg.levels[l]
+        S, Pt = lev["S"], lev["patches"]
+        upd = Pt.local_solve(lev["K"], v, rj)
+        if l == level and is_interior(Pt, v):
+            nv = 3 * Pt.nvel
+            x, t, _ = normalize_pair(rj[:nv], rj[nv:], upd[:nv], upd[nv:], S.h)
+            sink.append((x, t))
+        return upd
+    return local

@@ -175,4 +175,105 @@ class StokesMG:
         hist = [info.history[i] for i in range(min(info.iterations + 1, _lib.MAX_HISTORY))]
         return x, dict(iterations=info.iterations, converged=bool(info.converged), rel_residual=info.rel_residual,
                        nu=info.nu, history=hist, cg_iterations=info.cg_iterations, local_solves=info.local_solves,
-                       seconds=info.seconds)
+                       seconds=info.seconds, fallback_iteration=info.fallback_iteration)
+
+    # ------------------------------------------------------------ learned local solver
+    def mlp_dims(self):
+        """(d, P): patch vector length and parameter count for this degree."""
+        d, p = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.lib.mlp_dims(self._h, ctypes.byref(d), ctypes.byref(p)))
+        return d.value, p.value
+
+    def mlp_setup(self, max_rows):
+        """Allocates the MLP workspace (torch buffer) for batches of max_rows rows."""
+        torch = _torch()
+        nb = ctypes.c_size_t()
+        self._check(_lib.lib.mlp_workspace_size(self._h, int(max_rows), ctypes.byref(nb)))
+        self.mlp_workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self._check(_lib.lib.mlp_set_workspace(self._h, self.mlp_workspace.data_ptr(), self.mlp_workspace.numel(),
+                                               int(max_rows)))
+        self.mlp_rows = int(max_rows)
+
+    def mlp_init(self, seed=0):
+        self._check(_lib.lib.mlp_init(self._h, int(seed), self._stream()))
+
+    def mlp_get_state(self):
+        """(state, step): state = params | Adam m | Adam v (float32 device tensor)."""
+        torch = _torch()
+        _, P = self.mlp_dims()
+        st = torch.empty(3 * P, dtype=torch.float32, device=self.device)
+        step = ctypes.c_int64()
+        self._check(_lib.lib.mlp_get_state(self._h, st.data_ptr(), ctypes.byref(step), self._stream()))
+        return st, step.value
+
+    def mlp_set_state(self, state, step=0):
+        torch = _torch()
+        _, P = self.mlp_dims()
+        if state.dtype != torch.float32 or state.numel() != 3 * P or state.device != self.device:
+            raise ValueError(f"state must be a float32 tensor of {3 * P} entries on {self.device}")
+        state = state.contiguous()
+        self._check(_lib.lib.mlp_set_state(self._h, state.data_ptr(), int(step), self._stream()))
+
+    @staticmethod
+    def _mode(mode):
+        return {"bf16": 0, "f32": 1}[mode]
+
+    def _rows(self, t, name):
+        torch = _torch()
+        d, _ = self.mlp_dims()
+        if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != d or not t.is_contiguous() \
+                or t.device != self.device:
+            raise ValueError(f"{name} must be a contiguous float32 [rows x {d}] tensor on {self.device}")
+
+    def mlp_forward(self, X, mode="bf16"):
+        torch = _torch()
+        self._rows(X, "X")
+        Y = torch.empty_like(X)
+        self._check(_lib.lib.mlp_forward(self._h, self._mode(mode), X.data_ptr(), Y.data_ptr(), X.shape[0],
+                                         self._stream()))
+        return Y
+
+    def mlp_backward(self, X, T, mode="bf16"):
+        """(grads, loss): gradient of mean((net(X) - T)^2) and the loss (device tensors)."""
+        torch = _torch()
+        self._rows(X, "X")
+        self._rows(T, "T")
+        _, P = self.mlp_dims()
+        g = torch.empty(P, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        self._check(_lib.lib.mlp_backward(self._h, self._mode(mode), X.data_ptr(), T.data_ptr(), X.shape[0],
+                                          g.data_ptr(), loss.data_ptr(), self._stream()))
+        return g, loss
+
+    def mlp_adam_step(self, grads, lr):
+        self._check(_lib.lib.mlp_adam_step(self._h, grads.data_ptr(), float(lr), self._stream()))
+
+    def mlp_collect_pairs(self, b, X, T, n=0, x=None):
+        """One FP64 V-cycle for b capturing interior-patch pairs into rows n.. of X, T;
+        returns (new n, x)."""
+        torch = _torch()
+        self._vec(b, -1, "b")
+        self._rows(X, "X")
+        self._rows(T, "T")
+        if x is None:
+            x = torch.empty_like(b)
+        nn = ctypes.c_int64(int(n))
+        self._check(_lib.lib.mlp_collect_pairs(self._h, b.data_ptr(), x.data_ptr(), X.data_ptr(), T.data_ptr(),
+                                               min(X.shape[0], T.shape[0]), ctypes.byref(nn), self._stream()))
+        return nn.value, x
+
+    def mlp_train(self, X, T, n=None, epochs=1, batch=4096, lr=1e-3, seed=0, mode="bf16"):
+        """Trains on rows 0..n-1; returns the per-epoch mean losses."""
+        self._rows(X, "X")
+        self._rows(T, "T")
+        n = X.shape[0] if n is None else int(n)
+        hist = (ctypes.c_float * max(epochs, 1))()
+        self._check(_lib.lib.mlp_train(self._h, self._mode(mode), X.data_ptr(), T.data_ptr(), n, int(epochs),
+                                       int(batch), float(lr), int(seed), hist, self._stream()))
+        return [hist[i] for i in range(epochs)]
+
+    def set_local_solver(self, solver="exact", mode="bf16"):
+        self._check(_lib.lib.stokesmg_set_local_solver(self._h, {"exact": 0, "mlp": 1}[solver], self._mode(mode)))
+
+    def set_fallback(self, rho_ref):
+        self._check(_lib.lib.stokesmg_set_fallback(self._h, float(rho_ref)))

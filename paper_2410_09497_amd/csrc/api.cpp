@@ -9,6 +9,7 @@
 
 #include "apply.hpp"
 #include "handle.hpp"
+#include "mlp.hpp"
 #include "patch.hpp"
 #include "patch_tables.hpp"
 #include "stencil_tables.hpp"
@@ -78,6 +79,8 @@ int stokesmg_create(const stokesmg_config* cfg, stokesmg_t** out) {
     h->cg_counter = off;
     off = align256(off + 2 * sizeof(int));
     h->r_vec = off;
+    off = align256(off + size_t(level_total(h, L - 1)) * sizeof(double));
+    h->c_vec = off;
     off = align256(off + size_t(level_total(h, L - 1)) * sizeof(double));
     h->tro.resize(L);
     for (int l = 1; l < L; ++l) {
@@ -220,16 +223,8 @@ int patch_smooth(stokesmg_t* h, int level, int dtype, void* x, const void* b, in
         return h->fail(STOKESMG_EINVAL, "x, b and the workspace must not overlap");
     const bool f64 = dtype == STOKESMG_F64;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    void* r = h->ws + h->r_vec;
-    const void* tab = h->ws + (f64 ? h->tab_f64[level] : h->tab_f32[level]);
-    const void* ptab = h->ws + (f64 ? h->ptab_f64[level] : h->ptab_f32[level]);
-    int* counters = reinterpret_cast<int*>(h->ws + h->cg_counter);
     for (int s = 0; s < n_sweeps; ++s)
-        for (int c = 0; c < 8; ++c) {
-            SMG_HIP(h, smg::launch_apply(h->cfg.k, f64, true, x, b, r, tab, h->lv[level].n, st));
-            SMG_HIP(h, smg::launch_patch_solve(h->cfg.k, f64, x, r, ptab, h->lv[level].n, c, h->cfg.cg_rtol,
-                                               h->cfg.cg_max_it, counters, st));
-        }
+        if (int rc = smg::smooth_sweep(h, level, f64, x, b, st, nullptr)) return rc;
     return STOKESMG_OK;
 }
 

@@ -24,6 +24,7 @@ struct stokesmg {
     std::vector<size_t> tab_f64, tab_f32;    // per level
     std::vector<size_t> ptab_f64, ptab_f32;  // per level (patch tables; unused for n < 2)
     size_t r_vec = 0;                        // residual vector of the finest level (8 B per unknown)
+    size_t c_vec = 0;                        // correction vector of the finest level (pair capture)
     size_t cg_counter = 0;                   // two int counters: CG iterations, patch solves
     size_t ws_needed = 0;
 
@@ -44,6 +45,22 @@ struct stokesmg {
     // scratch regions (in doubles): coefficients / dot results, pressure moment, multi-dot partials
     static constexpr int kCoef = 0, kMoment = 64, kPartial = 2048, kPartialBlocks = 1024;
     static constexpr int kScratch = kPartial + kPartialBlocks * 64;
+
+    // learned local solver: caller-owned MLP workspace and offsets inside it (bytes)
+    struct Mlp {
+        char* ws = nullptr;
+        size_t bytes = 0;
+        int64_t rows = 0;          // max rows per batch / chunk
+        int d = 0, H = 256;
+        int64_t P = 0;             // parameter count
+        size_t params, grads, m, v, Z1, H1, Z2, H2, Y, dY, dZ2, dZ1, X, s, split, lossp, loss, colp, brows, acc;
+        size_t split_floats = 0;
+        int64_t step = 0;          // Adam steps taken
+        bool ready = false;        // parameters initialized or set
+    } mlp;
+    int local_solver = STOKESMG_LOCAL_EXACT;
+    int mlp_mode = STOKESMG_MLP_BF16;
+    double rho_ref = 0.0;
 
     int fail(int code, const std::string& msg) {
         err = msg;

@@ -1,0 +1,618 @@
+// Kernels of the per-patch MLP local solver, gfx950.
+//
+// GEMM: a workgroup of four waves owns a (32 TI) x (32 TJ) tile of C, each
+// wave a (16 TI) x (16 TJ) quarter built from 16 x 16 MFMA blocks
+// (v_mfma_f32_16x16x32_bf16 for BF16 operands, v_mfma_f32_16x16x4_f32 for FP32
+// operands).  Both operand tiles sit in LDS with k contiguous ([row][k]), so
+// a lane's fragment (8 consecutive k for BF16) is one 16-byte LDS read; the
+// next k-slab is prefetched into registers while the current one is
+// multiplied.  Split-K (deterministic: partial tiles, then a sum) keeps the
+// long-K weight-gradient products from running on a handful of CUs.
+#include "mlp_kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace smg {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int GBK = 32;     // k per slab
+constexpr int GNT = 256;    // threads per workgroup
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+template <typename TOP> struct Op;
+template <> struct Op<__bf16> {
+    static constexpr int PAD = 8;   // row stride 40 elements = 80 bytes
+};
+template <> struct Op<float> {
+    static constexpr int PAD = 4;   // row stride 36 floats
+};
+
+struct GemmArgs {
+    int M, N, K;
+    const float* A;
+    int lda;
+    const int* arows;
+    const float* B;
+    int ldb;
+    float* C;
+    int ldc;
+    const float* bias;
+    float* Z;
+    int ldz;
+    int kslabs_per_split;   // k slabs handled by one blockIdx.z
+    size_t split_stride;    // floats between the partial C of consecutive splits
+};
+
+// One operand tile of R rows x GBK k, R = 32 T: thread t fetches 16 elements
+// (R x GBK / GNT = 16 when T = 4, 8 when T = 2).
+template <int R, bool KCONTIG>
+struct TileLoader {
+    static constexpr int PER = R * GBK / GNT;   // elements per thread
+    float v[PER];
+
+    // KCONTIG: element (r, kk) at src[row(r) ld + k0 + kk]; else at src[row(k0 + kk) ld + r0 + r]
+    __device__ inline void load(const float* __restrict__ src, int ld, const int* __restrict__ rows, int r0,
+                                int rmax, int k0, int kmax, int t) {
+        if constexpr (KCONTIG) {
+            constexpr int TPR = GBK / PER;           // threads per row
+            const int r = t / TPR, kk = (t % TPR) * PER;
+            const int gr = r0 + r, gk = k0 + kk;
+            if (gr < rmax) {
+                const float* p = src + size_t(rows ? rows[gr] : gr) * ld + gk;
+                if (gk + PER <= kmax) {
+#pragma unroll
+                    for (int i = 0; i < PER; i += 4) {
+                        const float4 q = *reinterpret_cast<const float4*>(p + i);
+                        v[i] = q.x; v[i + 1] = q.y; v[i + 2] = q.z; v[i + 3] = q.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < PER; ++i) v[i] = (gk + i < kmax) ? p[i] : 0.0f;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < PER; ++i) v[i] = 0.0f;
+            }
+        } else {
+            constexpr int TPK = R / PER;             // threads per k
+            const int kk = t / TPK, r = (t % TPK) * PER;
+            const int gk = k0 + kk, gr = r0 + r;
+            if (gk < kmax) {
+                const float* p = src + size_t(rows ? rows[gk] : gk) * ld + gr;
+                if (gr + PER <= rmax) {
+#pragma unroll
+                    for (int i = 0; i < PER; i += 4) {
+                        const float4 q = *reinterpret_cast<const float4*>(p + i);
+                        v[i] = q.x; v[i + 1] = q.y; v[i + 2] = q.z; v[i + 3] = q.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < PER; ++i) v[i] = (gr + i < rmax) ? p[i] : 0.0f;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < PER; ++i) v[i] = 0.0f;
+            }
+        }
+    }
+
+    template <typename TOP>
+    __device__ inline void store(TOP* __restrict__ s, int t) const {
+        constexpr int LD = GBK + Op<TOP>::PAD;
+        if constexpr (KCONTIG) {
+            constexpr int TPR = GBK / PER;
+            const int r = t / TPR, kk = (t % TPR) * PER;
+            TOP* d = s + r * LD + kk;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) d[i] = TOP(v[i]);
+        } else {
+            constexpr int TPK = R / PER;
+            const int kk = t / TPK, r = (t % TPK) * PER;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) s[(r + i) * LD + kk] = TOP(v[i]);
+        }
+    }
+};
+
+template <typename TOP, int TI, int TJ, bool TA, bool TB, Epi EPI>
+__global__ void __launch_bounds__(GNT) gemm_kernel(GemmArgs g) {
+    constexpr int BM = 32 * TI, BN = 32 * TJ, LD = GBK + Op<TOP>::PAD;
+    __shared__ __attribute__((aligned(16))) TOP As[BM * LD];
+    __shared__ __attribute__((aligned(16))) TOP Bs[BN * LD];
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int nslab_total = (g.K + GBK - 1) / GBK;
+    const int s_begin = blockIdx.z * g.kslabs_per_split;
+    const int s_end = min(nslab_total, s_begin + g.kslabs_per_split);
+
+    // A element (m, k): !TA -> A[row(m) lda + k] (k contiguous); TA -> A[row(k) lda + m]
+    TileLoader<BM, !TA> la;
+    // B element (k, n): !TB -> B[k ldb + n] (n contiguous); TB -> B[n ldb + k]
+    TileLoader<BN, TB> lb;
+
+    f32x4 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    if (s_begin < s_end) {
+        la.load(g.A, g.lda, g.arows, m0, g.M, s_begin * GBK, g.K, t);
+        lb.load(g.B, g.ldb, nullptr, n0, g.N, s_begin * GBK, g.K, t);
+    }
+    const int fr = lane & 15, fq = lane >> 4;
+    for (int s = s_begin; s < s_end; ++s) {
+        __syncthreads();   // previous slab fully consumed
+        la.store(As, t);
+        lb.store(Bs, t);
+        __syncthreads();
+        if (s + 1 < s_end) {
+            la.load(g.A, g.lda, g.arows, m0, g.M, (s + 1) * GBK, g.K, t);
+            lb.load(g.B, g.ldb, nullptr, n0, g.N, (s + 1) * GBK, g.K, t);
+        }
+        if constexpr (sizeof(TOP) == 2) {
+            bf16x8 a[TI], b[TJ];
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * 16 * TI + i * 16 + fr) * LD + fq * 8]);
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(&Bs[(wn * 16 * TJ + j * 16 + fr) * LD + fq * 8]);
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < GBK / 4; ++q) {
+                float a[TI], b[TJ];
+#pragma unroll
+                for (int i = 0; i < TI; ++i) a[i] = As[(wm * 16 * TI + i * 16 + fr) * LD + 4 * q + fq];
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) b[j] = Bs[(wn * 16 * TJ + j * 16 + fr) * LD + 4 * q + fq];
+#pragma unroll
+                for (int i = 0; i < TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+
+    // C[row][col]: row = tile row + 4 (lane / 16) + e, col = tile col + lane % 16
+    float* C = g.C + blockIdx.z * g.split_stride;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int col = n0 + wn * 16 * TJ + j * 16 + fr;
+            if (col >= g.N) continue;
+            float bv = 0.0f;
+            if constexpr (EPI == Epi::Bias || EPI == Epi::BiasGelu) bv = g.bias[col];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + wm * 16 * TI + i * 16 + 4 * fq + e;
+                if (row >= g.M) continue;
+                float v = acc[i][j][e];
+                if constexpr (EPI == Epi::Bias) v += bv;
+                if constexpr (EPI == Epi::BiasGelu) {
+                    v += bv;
+                    if (g.Z) g.Z[size_t(row) * g.ldz + col] = v;
+                    v = gelu(v);
+                }
+                if constexpr (EPI == Epi::GeluGrad) v *= gelu_grad(g.Z[size_t(row) * g.ldz + col]);
+                C[size_t(row) * g.ldc + col] = v;
+            }
+        }
+}
+
+// C = sum over `splits` partial tiles (ld = ldc, stride `stride` floats)
+__global__ void split_sum_kernel(const float* __restrict__ P, int splits, size_t stride, int M, int N, int ldc,
+                                 float* __restrict__ C) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= size_t(M) * N) return;
+    const size_t row = i / N, col = i % N, off = row * ldc + col;
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += P[z * stride + off];
+    C[off] = s;
+}
+
+template <typename TOP, int TI, int TJ, Epi EPI>
+hipError_t gemm_dispatch_t(bool ta, bool tb, const GemmArgs& g, dim3 grid, hipStream_t st) {
+    if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<TOP, TI, TJ, false, false, EPI>), grid, dim3(GNT), 0, st, g);
+    else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<TOP, TI, TJ, false, true, EPI>), grid, dim3(GNT), 0, st, g);
+    else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<TOP, TI, TJ, true, false, EPI>), grid, dim3(GNT), 0, st, g);
+    else hipLaunchKernelGGL((gemm_kernel<TOP, TI, TJ, true, true, EPI>), grid, dim3(GNT), 0, st, g);
+    return hipGetLastError();
+}
+
+template <typename TOP, int TI, int TJ>
+hipError_t gemm_dispatch_e(Epi epi, bool ta, bool tb, const GemmArgs& g, dim3 grid, hipStream_t st) {
+    switch (epi) {
+        case Epi::Store: return gemm_dispatch_t<TOP, TI, TJ, Epi::Store>(ta, tb, g, grid, st);
+        case Epi::Bias: return gemm_dispatch_t<TOP, TI, TJ, Epi::Bias>(ta, tb, g, grid, st);
+        case Epi::BiasGelu: return gemm_dispatch_t<TOP, TI, TJ, Epi::BiasGelu>(ta, tb, g, grid, st);
+        case Epi::GeluGrad: return gemm_dispatch_t<TOP, TI, TJ, Epi::GeluGrad>(ta, tb, g, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_gemm(bool bf16, Epi epi, bool ta, bool tb, int M, int N, int K, const float* A, int lda,
+                       const int* arows, const float* B, int ldb, float* C, int ldc, const float* bias, float* Z,
+                       int ldz, float* split_ws, size_t split_ws_floats, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    GemmArgs g{M, N, K, A, lda, arows, B, ldb, C, ldc, bias, Z, ldz, 0, 0};
+    const int nslab = std::max(1, (K + GBK - 1) / GBK);
+    // 128 x 128 tiles when they still give two workgroups per CU, else 64 x 64
+    const bool big = size_t((M + 127) / 128) * ((N + 127) / 128) >= 512;
+    const int bt = big ? 128 : 64;
+    dim3 grid((N + bt - 1) / bt, (M + bt - 1) / bt, 1);
+    g.kslabs_per_split = nslab;
+    int splits = 1;
+    const size_t tiles = size_t(grid.x) * grid.y;
+    if (epi == Epi::Store && split_ws != nullptr && tiles < 256 && nslab >= 16) {
+        splits = int(std::min<size_t>({size_t(16), (512 + tiles - 1) / tiles, size_t(nslab / 4)}));
+        g.kslabs_per_split = (nslab + splits - 1) / splits;
+        splits = (nslab + g.kslabs_per_split - 1) / g.kslabs_per_split;
+        if (splits > 1 && size_t(splits) * M * ldc <= split_ws_floats) {
+            g.C = split_ws;
+            g.split_stride = size_t(M) * ldc;
+            grid.z = splits;
+        } else {
+            splits = 1;
+            g.kslabs_per_split = nslab;
+        }
+    }
+    hipError_t e;
+    if (big) e = bf16 ? gemm_dispatch_e<__bf16, 4, 4>(epi, ta, tb, g, grid, st)
+                      : gemm_dispatch_e<float, 4, 4>(epi, ta, tb, g, grid, st);
+    else e = bf16 ? gemm_dispatch_e<__bf16, 2, 2>(epi, ta, tb, g, grid, st)
+                  : gemm_dispatch_e<float, 2, 2>(epi, ta, tb, g, grid, st);
+    if (e != hipSuccess || splits == 1) return e;
+    const size_t total = size_t(M) * N;
+    hipLaunchKernelGGL(split_sum_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, split_ws, splits,
+                       g.split_stride, M, N, ldc, C);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- loss, sums, Adam
+
+namespace {
+
+__global__ void mse_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T, const int* __restrict__ trows,
+                                int rows, int cols, float* __restrict__ dY, double* __restrict__ partial) {
+    __shared__ double red[256];
+    const size_t total = size_t(rows) * cols;
+    const float scale = 2.0f / float(total);
+    double acc = 0.0;
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += size_t(gridDim.x) * blockDim.x) {
+        const size_t r = i / cols, c = i % cols;
+        const float d = Y[i] - T[size_t(trows ? trows[r] : r) * cols + c];
+        dY[i] = scale * d;
+        acc += double(d) * d;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void loss_final_kernel(const double* __restrict__ partial, int nb, double denom, float* __restrict__ out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) acc += partial[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = float(red[0] / denom);
+}
+
+__global__ void colsum_partial_kernel(const float* __restrict__ G, int ldg, int rows, int cols,
+                                      float* __restrict__ partial) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    const int per = (rows + gridDim.y - 1) / gridDim.y;
+    const int r0 = blockIdx.y * per, r1 = min(rows, r0 + per);
+    float s = 0.0f;
+    for (int r = r0; r < r1; ++r) s += G[size_t(r) * ldg + c];
+    partial[size_t(blockIdx.y) * cols + c] = s;
+}
+
+__global__ void colsum_final_kernel(const float* __restrict__ partial, int splits, int cols, float* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += partial[size_t(z) * cols + c];
+    out[c] = s;
+}
+
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps, float c1,
+                            float c2) {
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mse_grad(const float* Y, const float* T, const int* trows, int rows, int cols, float* dY,
+                           double* partial, float* loss_out, hipStream_t st) {
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(kLossBlocks), dim3(256), 0, st, Y, T, trows, rows, cols, dY, partial);
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, partial, kLossBlocks,
+                       double(rows) * double(cols), loss_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* G, int ldg, int rows, int cols, float* partial, float* out, hipStream_t st) {
+    if (cols <= 0) return hipSuccess;
+    const dim3 grid((cols + 255) / 256, kColsumSplit);
+    hipLaunchKernelGGL(colsum_partial_kernel, grid, dim3(256), 0, st, G, ldg, rows, cols, partial);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, partial, kColsumSplit,
+                       cols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t st) {
+    const int blocks = int(std::min<size_t>((n + 255) / 256, 2048));
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- patch gather / scatter
+
+namespace {
+
+struct PatchGeo {
+    int n, k, lc, m, nvel, size, N1;
+    size_t nc;
+    int cnt[3], first[3];
+};
+
+__host__ PatchGeo make_geo(int n, int k, int colour) {
+    PatchGeo g;
+    g.n = n; g.k = k; g.lc = 2 * k + 1; g.m = 2 * k + 2;
+    g.nvel = g.lc * g.m * g.m;
+    g.size = 3 * g.nvel + g.m * g.m * g.m;
+    g.N1 = n * (k + 1);
+    g.nc = size_t(g.N1 - 1) * g.N1 * g.N1;
+    for (int d = 0; d < 3; ++d) {
+        const int par = (colour >> d) & 1;
+        g.cnt[d] = interior_count_1d(n, par);
+        g.first[d] = par ? 3 : 2;
+    }
+    return g;
+}
+
+// global index of patch-local entry q of the patch around vertex v; pres = pressure row
+__device__ inline size_t patch_index(const PatchGeo& g, const int v[3], int q, bool& pres) {
+    const int base0 = (v[0] - 1) * (g.k + 1), base1 = (v[1] - 1) * (g.k + 1), base2 = (v[2] - 1) * (g.k + 1);
+    if (q < 3 * g.nvel) {
+        const int c = q / g.nvel, w = q - c * g.nvel;
+        const int l0 = c == 0 ? g.lc : g.m, l1 = c == 1 ? g.lc : g.m;
+        const int i0 = w % l0, i1 = (w / l0) % l1, i2 = w / (l0 * l1);
+        const int e0 = c == 0 ? g.N1 - 1 : g.N1, e1 = c == 1 ? g.N1 - 1 : g.N1;
+        pres = false;
+        return size_t(c) * g.nc + (i0 + base0) + size_t(e0) * ((i1 + base1) + size_t(e1) * (i2 + base2));
+    }
+    const int w = q - 3 * g.nvel;
+    const int i0 = w % g.m, i1 = (w / g.m) % g.m, i2 = w / (g.m * g.m);
+    pres = true;
+    return 3 * g.nc + (i0 + base0) + size_t(g.N1) * ((i1 + base1) + size_t(g.N1) * (i2 + base2));
+}
+
+__device__ inline void patch_vertex(const PatchGeo& g, int p, int v[3]) {
+    const int a0 = p % g.cnt[0], a1 = (p / g.cnt[0]) % g.cnt[1], a2 = p / (g.cnt[0] * g.cnt[1]);
+    v[0] = g.first[0] + 2 * a0;
+    v[1] = g.first[1] + 2 * a1;
+    v[2] = g.first[2] + 2 * a2;
+}
+
+__device__ inline double block_sum(double x, double* red) {
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) patch_gather_kernel(const T* __restrict__ r, PatchGeo g, int p0,
+                                                           float* __restrict__ X, int ldx, float* __restrict__ s) {
+    __shared__ double red[256];
+    int v[3];
+    patch_vertex(g, p0 + blockIdx.x, v);
+    const double h = 1.0 / g.n, ih = g.n, ih2 = double(g.n) * g.n;
+    (void)h;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < g.size; q += 256) {
+        bool pres;
+        const size_t gi = patch_index(g, v, q, pres);
+        const double val = double(r[gi]) * (pres ? ih2 : ih);
+        acc += val * val;
+    }
+    const double nrm = sqrt(block_sum(acc, red));
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    float* row = X + size_t(blockIdx.x) * ldx;
+    for (int q = threadIdx.x; q < g.size; q += 256) {
+        bool pres;
+        const size_t gi = patch_index(g, v, q, pres);
+        row[q] = float(double(r[gi]) * (pres ? ih2 : ih) * inv);
+    }
+    if (threadIdx.x == 0) s[blockIdx.x] = float(nrm);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) patch_scatter_kernel(T* __restrict__ x, PatchGeo g, int p0,
+                                                            const float* __restrict__ Y, int ldy,
+                                                            const float* __restrict__ s) {
+    int v[3];
+    patch_vertex(g, p0 + blockIdx.x, v);
+    const float sc = s[blockIdx.x];
+    if (sc == 0.0f) return;
+    const float* row = Y + size_t(blockIdx.x) * ldy;
+    for (int q = threadIdx.x; q < g.size; q += 256) {
+        bool pres;
+        const size_t gi = patch_index(g, v, q, pres);
+        const double val = double(sc) * row[q] * (pres ? double(g.n) : 1.0);
+        x[gi] = T(double(x[gi]) + val);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) patch_gather_diff_kernel(const T* __restrict__ xn, const T* __restrict__ xo,
+                                                                PatchGeo g, int p0, float* __restrict__ Tt, int ldt,
+                                                                const float* __restrict__ s) {
+    int v[3];
+    patch_vertex(g, p0 + blockIdx.x, v);
+    const float sc = s[blockIdx.x];
+    const double inv = sc > 0.0f ? 1.0 / double(sc) : 0.0;
+    const double h = 1.0 / g.n;
+    float* row = Tt + size_t(blockIdx.x) * ldt;
+    for (int q = threadIdx.x; q < g.size; q += 256) {
+        bool pres;
+        const size_t gi = patch_index(g, v, q, pres);
+        row[q] = float((double(xn[gi]) - (xo ? double(xo[gi]) : 0.0)) * (pres ? h : 1.0) * inv);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_patch_gather(bool f64, const void* r, int n, int k, int colour, int p0, int np, float* X, int ldx,
+                               float* s, hipStream_t st) {
+    const PatchGeo g = make_geo(n, k, colour);
+    if (np <= 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(patch_gather_kernel<double>, dim3(np), dim3(256), 0, st,
+                                static_cast<const double*>(r), g, p0, X, ldx, s);
+    else hipLaunchKernelGGL(patch_gather_kernel<float>, dim3(np), dim3(256), 0, st, static_cast<const float*>(r), g,
+                            p0, X, ldx, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_patch_scatter(bool f64, void* x, int n, int k, int colour, int p0, int np, const float* Y, int ldy,
+                                const float* s, hipStream_t st) {
+    const PatchGeo g = make_geo(n, k, colour);
+    if (np <= 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(patch_scatter_kernel<double>, dim3(np), dim3(256), 0, st, static_cast<double*>(x), g,
+                                p0, Y, ldy, s);
+    else hipLaunchKernelGGL(patch_scatter_kernel<float>, dim3(np), dim3(256), 0, st, static_cast<float*>(x), g, p0,
+                            Y, ldy, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_patch_gather_diff(bool f64, const void* xnew, const void* xold, int n, int k, int colour, int p0,
+                                    int np, float* T, int ldt, const float* s, hipStream_t st) {
+    const PatchGeo g = make_geo(n, k, colour);
+    if (np <= 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(patch_gather_diff_kernel<double>, dim3(np), dim3(256), 0, st,
+                                static_cast<const double*>(xnew), static_cast<const double*>(xold), g, p0, T, ldt, s);
+    else hipLaunchKernelGGL(patch_gather_diff_kernel<float>, dim3(np), dim3(256), 0, st,
+                            static_cast<const float*>(xnew), static_cast<const float*>(xold), g, p0, T, ldt, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- training helpers
+
+namespace {
+
+__device__ inline uint64_t mix64(uint64_t z) {
+    // SplitMix64 output function (Steele, Lea & Flood 2014)
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+// keyed balanced Feistel bijection of [0, 2^(2 half)), four rounds
+__device__ inline uint64_t feistel(uint64_t x, int half, uint64_t key) {
+    const uint64_t mask = (uint64_t(1) << half) - 1;
+    uint64_t L = x >> half, R = x & mask;
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t F = mix64(R ^ (key + 0x9e3779b97f4a7c15ULL * uint64_t(r + 1))) & mask;
+        const uint64_t nL = R;
+        R = L ^ F;
+        L = nL;
+    }
+    return (L << half) | R;
+}
+
+__global__ void batch_rows_kernel(int* __restrict__ rows, int64_t start, int count, int64_t n, int half,
+                                  uint64_t key) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    // cycle walking: the orbit of start + i < n returns below n
+    uint64_t y = uint64_t(start + i);
+    do {
+        y = feistel(y, half, key);
+    } while (y >= uint64_t(n));
+    rows[i] = int(y);
+}
+
+template <typename T>
+__global__ void add_kernel(T* __restrict__ x, const T* __restrict__ c, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+        x[i] += c[i];
+}
+
+__global__ void accumulate_kernel(const float* __restrict__ v, double* __restrict__ acc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *acc += double(*v);
+}
+
+}  // namespace
+
+hipError_t launch_batch_rows(int* rows, int64_t start, int count, int64_t n, uint64_t key, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int bits = 2;
+    while ((int64_t(1) << bits) < n) ++bits;
+    bits += bits & 1;
+    hipLaunchKernelGGL(batch_rows_kernel, dim3((count + 255) / 256), dim3(256), 0, st, rows, start, count, n,
+                       bits / 2, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(bool f64, void* x, const void* c, size_t n, hipStream_t st) {
+    const int blocks = int(std::min<size_t>((n + 255) / 256, 4096));
+    if (blocks == 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(add_kernel<double>, dim3(blocks), dim3(256), 0, st, static_cast<double*>(x),
+                                static_cast<const double*>(c), n);
+    else hipLaunchKernelGGL(add_kernel<float>, dim3(blocks), dim3(256), 0, st, static_cast<float*>(x),
+                            static_cast<const float*>(c), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const float* v, double* acc, hipStream_t st) {
+    hipLaunchKernelGGL(accumulate_kernel, dim3(1), dim3(64), 0, st, v, acc);
+    return hipGetLastError();
+}
+
+}  // namespace smg

@@ -15,28 +15,28 @@ int count_parity(int n, int parity) {
 
 template <int K, typename T>
 hipError_t launch(void* x, const void* r, const void* ptab, int n, int colour, double rtol, int maxit, int* counters,
-                  hipStream_t st) {
+                  bool bonly, hipStream_t st) {
     const int cx = count_parity(n, colour & 1), cy = count_parity(n, (colour >> 1) & 1),
               cz = count_parity(n, (colour >> 2) & 1);
     const int grid = cx * cy * cz;
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL((patch_solve_kernel<K, T>), dim3(grid), dim3(PatchShape<K>::NT), 0, st, static_cast<T*>(x),
                        static_cast<const T*>(r), static_cast<const T*>(ptab), n, colour, cx, cy, T(rtol), maxit,
-                       counters);
+                       counters, int(bonly));
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_patch_solve(int k, bool f64, void* x, const void* r, const void* ptab, int n, int colour,
-                              double cg_rtol, int cg_max_it, int* counters, hipStream_t st) {
+                              double cg_rtol, int cg_max_it, int* counters, bool boundary_only, hipStream_t st) {
     switch (k) {
-        case 1: return f64 ? launch<1, double>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, st)
-                           : launch<1, float>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, st);
-        case 2: return f64 ? launch<2, double>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, st)
-                           : launch<2, float>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, st);
-        case 3: return f64 ? launch<3, double>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, st)
-                           : launch<3, float>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, st);
+        case 1: return f64 ? launch<1, double>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st)
+                           : launch<1, float>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st);
+        case 2: return f64 ? launch<2, double>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st)
+                           : launch<2, float>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st);
+        case 3: return f64 ? launch<3, double>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st)
+                           : launch<3, float>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st);
         default: return hipErrorInvalidValue;
     }
 }

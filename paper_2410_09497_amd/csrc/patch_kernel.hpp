@@ -171,7 +171,7 @@ struct PatchIndex {
 template <int K, typename T>
 __global__ void __launch_bounds__(256)
 patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restrict__ tab, int n, int colour,
-                   int cntx, int cnty, T cg_rtol, int cg_maxit, int* __restrict__ counters) {
+                   int cntx, int cnty, T cg_rtol, int cg_maxit, int* __restrict__ counters, int boundary_only) {
     using P = PatchShape<K>;
     using PT = PatchTab<K>;
     constexpr int NV = P::NV, NP = P::NP, NC = P::NC, ND = P::ND;
@@ -190,6 +190,7 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     const int tx = (vx == 1 ? 1 : 0) + (vx == n - 1 ? 2 : 0);
     const int ty = (vy == 1 ? 1 : 0) + (vy == n - 1 ? 2 : 0);
     const int tz = (vz == 1 ? 1 : 0) + (vz == n - 1 ? 2 : 0);
+    if (boundary_only && (tx | ty | tz) == 0) return;   // whole workgroup: no barrier reached yet
     const int N1 = n * P::M;
     PatchIndex gi{N1, (vx - 1) * P::M, (vy - 1) * P::M, (vz - 1) * P::M, size_t(N1 - 1) * N1 * N1};
 

@@ -3,6 +3,7 @@
 // every vector operation is a device kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -11,13 +12,14 @@
 #include "apply.hpp"
 #include "handle.hpp"
 #include "mg_kernels.hpp"
+#include "mlp.hpp"
 #include "patch.hpp"
 
 namespace {
 
 using smg::Rows1D;
 
-int vcycle_level(stokesmg* h, int l, bool f64, const void* b, void* x, hipStream_t st) {
+int vcycle_level(stokesmg* h, int l, bool f64, const void* b, void* x, hipStream_t st, const smg::Capture* cap) {
     if (l == 0) {
         if (h->coarse_pinv.empty()) return h->fail(STOKESMG_EUNSUPPORTED, "coarsest level too large for the dense solve");
         SMG_HIP(h, smg::launch_coarse_gemv(f64, reinterpret_cast<const double*>(h->ws + h->coarse_off), b, x, h->N0, st));
@@ -26,19 +28,11 @@ int vcycle_level(stokesmg* h, int l, bool f64, const void* b, void* x, hipStream
     const int n = h->lv[l].n, k = h->cfg.k;
     const size_t N = size_t(level_total(h, l));
     const void* tab = h->ws + (f64 ? h->tab_f64[l] : h->tab_f32[l]);
-    const void* ptab = h->ws + (f64 ? h->ptab_f64[l] : h->ptab_f32[l]);
     void* r = h->ws + h->r_vec;
-    int* counters = reinterpret_cast<int*>(h->ws + h->cg_counter);
-    auto sweep = [&]() -> int {
-        for (int c = 0; c < 8; ++c) {
-            SMG_HIP(h, smg::launch_apply(k, f64, true, x, b, r, tab, n, st));
-            SMG_HIP(h, smg::launch_patch_solve(k, f64, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters, st));
-        }
-        return STOKESMG_OK;
-    };
+    const smg::Capture* lc = (l == h->n_levels - 1) ? cap : nullptr;
     // pre-smoothing from x = 0
     SMG_HIP(h, smg::launch_zero(f64, x, N, st));
-    if (int rc = sweep()) return rc;
+    if (int rc = smg::smooth_sweep(h, l, f64, x, b, st, lc)) return rc;
     // coarse-grid correction: b_{l-1} = P^T (b - K x), x += P P_{l-1}^{-1} b_{l-1}
     SMG_HIP(h, smg::launch_apply(k, f64, true, x, b, r, tab, n, st));
     const auto& o = h->tro[l];
@@ -50,13 +44,13 @@ int vcycle_level(stokesmg* h, int l, bool f64, const void* b, void* x, hipStream
                                     reinterpret_cast<const double*>(w + o.rd_w), o.wrd,
                                     reinterpret_cast<const int*>(w + o.rc_i),
                                     reinterpret_cast<const double*>(w + o.rc_w), o.wrc, st));
-    if (int rc = vcycle_level(h, l - 1, f64, bc, xc, st)) return rc;
+    if (int rc = vcycle_level(h, l - 1, f64, bc, xc, st, cap)) return rc;
     SMG_HIP(h, smg::launch_transfer(f64, true, xc, x, N1f, N1c, reinterpret_cast<const int*>(w + o.pd_i),
                                     reinterpret_cast<const double*>(w + o.pd_w), o.wpd,
                                     reinterpret_cast<const int*>(w + o.pc_i),
                                     reinterpret_cast<const double*>(w + o.pc_w), o.wpc, st));
     // post-smoothing
-    return sweep();
+    return smg::smooth_sweep(h, l, f64, x, b, st, lc);
 }
 
 int check_mg(stokesmg* h) {
@@ -133,6 +127,15 @@ void load_1d(const smg::Ref1D& r, int n, bool cont, int g, double gamma, std::ve
 
 }  // namespace
 
+namespace smg {
+
+int vcycle_run(stokesmg* h, bool f64, const void* b, void* x, hipStream_t st, const Capture* cap) {
+    if (int rc = check_mg(h)) return rc;
+    return vcycle_level(h, h->n_levels - 1, f64, b, x, st, cap);
+}
+
+}  // namespace smg
+
 extern "C" {
 
 int vcycle(stokesmg_t* h, int dtype, const void* b, void* x, void* stream) {
@@ -145,7 +148,7 @@ int vcycle(stokesmg_t* h, int dtype, const void* b, void* x, void* stream) {
     if (ranges_overlap(b, bytes, x, bytes) || ranges_overlap(x, bytes, h->ws, h->ws_bytes) ||
         ranges_overlap(b, bytes, h->ws, h->ws_bytes))
         return h->fail(STOKESMG_EINVAL, "b, x and the workspace must not overlap");
-    return vcycle_level(h, L, dtype == STOKESMG_F64, b, x, static_cast<hipStream_t>(stream));
+    return vcycle_level(h, L, dtype == STOKESMG_F64, b, x, static_cast<hipStream_t>(stream), nullptr);
 }
 
 int stokesmg_solve_workspace_size(const stokesmg_t* h, int restart, size_t* bytes) {
@@ -185,7 +188,19 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
     const bool f32 = vcycle_dtype == STOKESMG_F32;
     const void* tab64 = h->ws + h->tab_f64[L];
     double* coef = reinterpret_cast<double*>(h->ws + h->scratch_off);   // device coefficients (<= 64)
-    if (info) std::memset(info, 0, sizeof(*info));
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->fallback_iteration = -1;
+    }
+    // learned local solver: monitor the contraction and fall back to the exact solver for the rest
+    // of the solve once it exceeds max(2 rho_ref, 1e-3) or the residual grows
+    const int solver0 = h->local_solver;
+    int fallback_at = -1;
+    struct Restore {
+        stokesmg* h;
+        int s;
+        ~Restore() { h->local_solver = s; }
+    } restore{h, solver0};
     int64_t it0 = 0, so0 = 0;
     {
         int c[2];
@@ -225,10 +240,10 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
             // z_j = P^{-1} v_j (FP32 V-cycle: convert on entry and exit, the precision boundary)
             if (f32) {
                 SMG_HIP(h, smg::launch_convert(true, vj, vin, N, st));
-                if (int rc = vcycle_level(h, L, false, vin, vout, st)) return rc;
+                if (int rc = vcycle_level(h, L, false, vin, vout, st, nullptr)) return rc;
                 SMG_HIP(h, smg::launch_convert(false, vout, zj, N, st));
             } else {
-                if (int rc = vcycle_level(h, L, true, vj, zj, st)) return rc;
+                if (int rc = vcycle_level(h, L, true, vj, zj, st, nullptr)) return rc;
             }
             // w = K z_j, orthogonalized twice against V_0..V_j (classical Gram-Schmidt, twice)
             SMG_HIP(h, smg::launch_apply(k, true, false, zj, nullptr, w, tab64, n, st));
@@ -265,6 +280,14 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
             ++it;
             jdone = j + 1;
             hist.push_back(std::fabs(g[j + 1]) / bnorm);
+            if (h->local_solver == STOKESMG_LOCAL_MLP) {
+                const double rho = hist[hist.size() - 1] / hist[hist.size() - 2];
+                const bool bad = rho > 1.0 || (h->rho_ref > 0.0 && rho > std::max(2.0 * h->rho_ref, 1e-3));
+                if (bad) {
+                    h->local_solver = STOKESMG_LOCAL_EXACT;
+                    fallback_at = it;
+                }
+            }
             if (hist.back() <= rtol || it >= max_it) break;
         }
         // x += Z y, H(0:j, 0:j) y = g(0:j)
@@ -300,6 +323,7 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
         info->cg_iterations = c[0] - it0;
         info->local_solves = c[1] - so0;
         info->seconds = std::chrono::duration<double>(t1 - t0).count();
+        info->fallback_iteration = fallback_at;
     }
     return conv ? STOKESMG_OK : h->fail(STOKESMG_ENOTCONV, "FGMRES reached max_it");
 }
