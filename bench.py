@@ -28,15 +28,17 @@ if ROOT not in sys.path:
 
 METRIC = "Stokes apply DoF/s (%HBM roofline); time to 1e-8 res, FP64 MG vs FP32/learned MG"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2410_09497_amd/csrc/apply_kernel.hpp", "paper_2410_09497_amd/csrc/apply.hip",
-                  "paper_2410_09497_amd/csrc/stencil_tables.hpp"]
+KERNEL_SOURCES = ["paper_2410_09497_amd/csrc/apply_kernel.hpp", "paper_2410_09497_amd/csrc/apply_launch.hpp",
+                  "paper_2410_09497_amd/csrc/apply_common.cpp", "paper_2410_09497_amd/csrc/stencil_tables.hpp",
+                  "paper_2410_09497_amd/csrc/apply_k{k}.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic.json")
 
 
-def kernel_source_hash():
+def kernel_source_hash(k):
+    """Hash of the sources that define the operator kernel of degree k."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
+        with open(os.path.join(ROOT, f.format(k=k)), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -48,11 +50,9 @@ def measured_traffic(k, n, dtype, ndof):
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
-        return None
     key = f"k{k}_n{n}_{dtype}"
     ent = rec.get("cases", {}).get(key)
-    if not ent:
+    if not ent or ent.get("kernel_source_hash") != kernel_source_hash(k):
         return None
     return ent.get("hbm_bytes_per_launch")
 
