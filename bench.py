@@ -12,8 +12,16 @@ operator on a bounded sample of the same problem family on this host.
 Inputs rotate over enough (x, y) pairs that the working set exceeds the
 256 MB Infinity Cache, so the figure is an HBM figure.
 
+Second part of the metric, `solve`: time to a relative residual of 1e-8 of
+FGMRES(30) preconditioned by the V-cycle on 128^3 cells, RT_2 (226 M
+unknowns, 8 levels), for the manufactured sine problem: all-FP64 multigrid,
+FP32 V-cycle (mixed precision), and FP32 V-cycle with the learned local
+solver (trained first on ~10^6 pairs captured from exact V-cycles on 32^3
+cells with random smooth right-hand sides) with the exact-solver fallback.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 2] [--n 64]
-                       [--dtype f64|f32] [--no-cpu-baseline]
+                       [--dtype f64|f32] [--no-cpu-baseline] [--no-solve]
+                       [--solve-n 128]
 """
 import argparse
 import hashlib
@@ -86,6 +94,87 @@ def cpu_baseline(k):
                       f"{len(os.sched_getaffinity(0))} usable cores"}
 
 
+def solve_section(dev, k, n_solve, log):
+    """FP64 MG vs FP32 MG vs learned MG: time to 1e-8 (wall time of solve())."""
+    import numpy as np
+    import torch
+    from paper_2410_09497_amd import StokesMG
+
+    out = {"workload": f"FGMRES(30) + V(1,1) to 1e-8 on {n_solve}^3 cells, RT_{k}/DG Q_{k}, manufactured sine "
+                       "problem, levels down to 1^3; local Schur CG rtol 1e-3, at most 15 iterations"}
+    mg = StokesMG(n_solve, k, cg_rtol=1e-3, cg_max_it=15, device=dev)
+    out["unknowns"] = mg.ndof()
+    b = mg.rhs_manufactured()
+    runs = {}
+    for name, vd in (("fp64_mg", "f64"), ("fp32_mg", "f32")):
+        x, info = mg.solve(b, rtol=1e-8, max_it=60, vcycle_dtype=vd, allow_notconv=True)
+        runs[name] = {"seconds": info["seconds"], "iterations": info["iterations"],
+                      "rel_residual": info["rel_residual"], "nu": info["nu"],
+                      "history": info["history"],
+                      "avg_local_cg": info["cg_iterations"] / max(info["local_solves"], 1)}
+        log(f"[bench] {name}: {info['seconds']:.3f} s, {info['iterations']} iterations")
+    h = runs["fp32_mg"]["history"]
+    rho_ref = h[-1] ** (1.0 / max(runs["fp32_mg"]["iterations"], 1))
+
+    # learned local solver: pairs from exact FP64 V-cycles on 32^3 cells, training, then the solve
+    nt = 32
+    tr = StokesMG(nt, k, cg_rtol=1e-10, cg_max_it=200, device=dev)
+    tr.mlp_setup(65536)
+    tr.mlp_init(seed=0)
+    d, _ = tr.mlp_dims()
+    cap = 1_000_000
+    X = torch.empty(cap, d, dtype=torch.float32, device=dev)
+    T = torch.empty_like(X)
+    cnt, s = 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while cnt < cap:
+        f = tr.rhs_fourier(seed=s)
+        cnt, _ = tr.mlp_collect_pairs(f, X, T, n=cnt)
+        s += 1
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    epochs, batch = 20, 4096
+    t0 = time.perf_counter()
+    hist = tr.mlp_train(X, T, n=cnt, epochs=epochs, batch=batch, lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    d_h = 256
+    flop_per_sample = 3 * 2 * (d * d_h + d_h * d_h + d_h * d)
+    state, step = tr.mlp_get_state()
+    del tr, X, T
+    torch.cuda.empty_cache()
+    out["training"] = {"pairs": cnt, "v_cycles": s, "collect_seconds": t_collect, "epochs": epochs, "batch": batch,
+                       "train_seconds": t_train, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+                       "samples_per_s": epochs * cnt / t_train,
+                       "tflops": epochs * cnt * flop_per_sample / t_train / 1e12,
+                       "mfma_peak_tflops_bf16": 2500.0,
+                       "workload": f"pairs from exact FP64 V-cycles on {nt}^3 cells, RT_{k}, random smooth "
+                                   "right-hand sides (8 Fourier modes per component, wavenumbers 1..8); "
+                                   f"MLP {d}-256-256-{d}, GELU, BF16 operands, FP32 accumulation, Adam"}
+    log(f"[bench] training: {cnt} pairs, {t_train:.2f} s for {epochs} epochs")
+    mg.mlp_setup(65536)
+    mg.mlp_set_state(state, step)
+    mg.set_local_solver("mlp", "bf16")
+    mg.set_fallback(rho_ref)
+    x, info = mg.solve(b, rtol=1e-8, max_it=60, vcycle_dtype="f32", allow_notconv=True)
+    mg.set_local_solver("exact")
+    fb = info["fallback_iteration"]
+    runs["learned_mg"] = {"seconds": info["seconds"], "iterations": info["iterations"],
+                          "rel_residual": info["rel_residual"], "history": info["history"],
+                          "fallback_iteration": fb, "rho_ref": rho_ref,
+                          "fallback_bound": max(2 * rho_ref, 1e-3),
+                          "learned_contraction": (info["history"][1] if fb != 0 and len(info["history"]) > 1
+                                                  else None)}
+    log(f"[bench] learned_mg: {info['seconds']:.3f} s, {info['iterations']} iterations, fallback after {fb}")
+    out.update(runs)
+    out["fp32_speedup_vs_fp64"] = runs["fp64_mg"]["seconds"] / runs["fp32_mg"]["seconds"]
+    out["learned_speedup_vs_fp64"] = runs["fp64_mg"]["seconds"] / runs["learned_mg"]["seconds"]
+    del mg
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +184,8 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--solve-n", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the method's hot path here is single-GPU "
@@ -178,6 +269,11 @@ def main():
         "context": "paper (A100, FP64): > 1 GDoF/s operator evaluation; 0.535 ns/DoF = 1.87 GDoF/s "
                    "for RT_2 on 32^3 (Table vs_poisson)",
     }
+    del xs, ys, cbuf_a, cbuf_b, mg
+    torch.cuda.empty_cache()
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    if not args.no_solve:
+        out["solve"] = solve_section(dev, k, args.solve_n, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(k)
     print(json.dumps(out))

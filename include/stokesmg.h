@@ -150,7 +150,8 @@ typedef struct {
     long long cg_iterations;  /* local Schur CG iterations during the solve */
     long long local_solves;   /* local patch solves during the solve */
     double seconds;           /* wall time of the solve call */
-    int    fallback_iteration;/* FGMRES step after which the learned solver was replaced (-1: never) */
+    int    fallback_iteration;/* learned local solver: FGMRES steps done with it before the exact solver
+                                 took over for the rest of the solve (-1: never) */
 } stokesmg_info;
 
 /* Bytes of the caller-owned solve workspace for FGMRES(restart), 1 <= restart <= 60:
@@ -176,6 +177,16 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
  * p = cos(pi x) cos(pi y) cos(pi z), f = -Laplace u + grad p. */
 #define STOKESMG_PROBLEM_SINE 0
 int stokesmg_rhs_manufactured(stokesmg_t* h, int level, int problem, double* b, void* stream);
+
+/* Right-hand side (f, phi) of a smooth random body force (FP64 device
+ * vector on level `level`), no boundary data, pressure rows zero:
+ * f_c(x) = sum_m amp[c][m] cos(pi kappa[c][m] . x + theta[c][m]), c = 0..2,
+ * m < n_modes.  kappa: host int array [3][n_modes][3]; amp, theta: host double
+ * arrays [3][n_modes].  Gauss quadrature with k+2 points per direction
+ * (the force is expanded into separable products of cosines and sines).
+ * Synchronizes `stream`. */
+int stokesmg_rhs_fourier(stokesmg_t* h, int level, int n_modes, const int* kappa, const double* amp,
+                         const double* theta, double* b, void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned local solver (an extension; the paper's local solvers are exact).
@@ -206,7 +217,9 @@ int stokesmg_rhs_manufactured(stokesmg_t* h, int level, int problem, double* b, 
 #define STOKESMG_MLP_F32  1
 
 #define STOKESMG_LOCAL_EXACT 0   /* Schur complement + fast diagonalization (Sec. 3.2) */
-#define STOKESMG_LOCAL_MLP   1   /* network on interior patches, exact solve on the others */
+#define STOKESMG_LOCAL_MLP   1   /* network on interior patches, exact solve on the others; the
+                                    learned patch pressure is projected to zero coefficient mean,
+                                    as the exact correction (orthogonal to the kernel of K_j) is */
 
 /* d (network width in and out) and P (parameter count) for the handle's degree. */
 int mlp_dims(const stokesmg_t* h, int64_t* d, int64_t* n_params);
@@ -254,15 +267,19 @@ int mlp_collect_pairs(stokesmg_t* h, const double* b, double* x, float* X, float
 int mlp_train(stokesmg_t* h, int mode, const float* X, const float* T, int64_t n, int epochs, int batch, float lr,
               uint64_t seed, float* loss_hist, void* stream);
 
-/* Local solver used by patch_smooth, vcycle and solve from now on, and the
- * network's precision.  STOKESMG_LOCAL_MLP needs an MLP workspace. */
-int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode);
+/* Local solver used by patch_smooth, vcycle and solve from now on, the
+ * network's precision, and a damping factor in (0, 1] applied to the learned
+ * corrections (1 = undamped).  STOKESMG_LOCAL_MLP needs an MLP workspace
+ * with parameters. */
+int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode, double mlp_damping);
 
 /* Fallback of the learned solver inside solve(): with the MLP local solver,
- * after FGMRES step j (j >= 1) with contraction rho_j = res_j / res_{j-1}, the
- * rest of the solve uses the exact local solver when rho_j > max(2 rho_ref,
- * 1e-3) or the residual estimate grew.  rho_ref <= 0 disables the rho test
- * (growth still triggers). */
+ * after FGMRES step j with contraction rho_j = res_j / res_{j-1} of the
+ * residual estimate, the rest of the solve uses the exact local solver when
+ * rho_j >= max(2 rho_ref, 1e-3) (rho_ref > 0: the plain method's measured
+ * contraction) or, for rho_ref <= 0, when rho_j >= 1 (no progress).  A
+ * preconditioned vector with non-finite entries also triggers it (that step
+ * is dropped).  FGMRES then restarts from the current iterate. */
 int stokesmg_set_fallback(stokesmg_t* h, double rho_ref);
 
 #ifdef __cplusplus

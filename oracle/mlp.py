@@ -93,7 +93,8 @@ def is_interior(Pt, v):
 
 def learned_local(mg, params):
     """Local-solver callback for Multigrid.smooth: the network on interior
-    patches (scaled as in the module doc), the pseudo-inverse elsewhere."""
+    patches (scaled as in the module doc, patch pressure projected to zero
+    coefficient mean), the pseudo-inverse elsewhere."""
     def local(l, v, rj):
         lev = mg.levels[l]
         S, Pt = lev["S"], lev["patches"]
@@ -105,7 +106,9 @@ def learned_local(mg, params):
             return np.zeros_like(rj)
         y, _ = forward(params, x[None, :])
         U, P = denormalize(y[0], s, nv, S.h)
-        return np.concatenate([U, P])
+        # the exact correction is orthogonal to the kernel of K_j (constant patch
+        # pressure); the learned one is projected the same way
+        return np.concatenate([U, P - P.mean()])
     return local
 
 

@@ -47,6 +47,7 @@ class StokesMG:
             raise StokesMGError(rc, "stokesmg_create rejected the configuration")
         self._h = h
         self._L = _lib            # keeps the library alive until this handle is released
+        self._destroy = _lib.lib.stokesmg_destroy   # still callable during interpreter shutdown
         self.n_cells, self.k, self.n_levels = n_cells, k, n_levels
         self.device = torch.device(device)
         nb = ctypes.c_size_t()
@@ -58,9 +59,9 @@ class StokesMG:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        L = getattr(self, "_L", None)
-        if h is not None and h.value and L is not None:
-            L.lib.stokesmg_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self._h = None
 
     def _stream(self):
@@ -150,6 +151,21 @@ class StokesMG:
         level = level % self.n_levels
         b = torch.empty(self.ndof(level), dtype=torch.float64, device=self.device)
         self._check(_lib.lib.stokesmg_rhs_manufactured(self._h, level, problem, b.data_ptr(), self._stream()))
+        return b
+
+    def rhs_fourier(self, seed, level=-1, n_modes=8):
+        """Right-hand side of the random smooth force of synth.fourier_modes(seed)."""
+        import numpy as np
+        from .synth import fourier_modes
+        torch = _torch()
+        level = level % self.n_levels
+        kappa, amp, theta = fourier_modes(seed, n_modes=n_modes)
+        kappa = np.ascontiguousarray(kappa, dtype=np.int32)
+        amp = np.ascontiguousarray(amp, dtype=np.float64)
+        theta = np.ascontiguousarray(theta, dtype=np.float64)
+        b = torch.empty(self.ndof(level), dtype=torch.float64, device=self.device)
+        self._check(_lib.lib.stokesmg_rhs_fourier(self._h, level, n_modes, kappa.ctypes.data, amp.ctypes.data,
+                                                  theta.ctypes.data, b.data_ptr(), self._stream()))
         return b
 
     def solve(self, b, rtol=1e-8, max_it=100, restart=30, vcycle_dtype="f64", x=None, allow_notconv=False):
@@ -272,8 +288,9 @@ class StokesMG:
                                        int(batch), float(lr), int(seed), hist, self._stream()))
         return [hist[i] for i in range(epochs)]
 
-    def set_local_solver(self, solver="exact", mode="bf16"):
-        self._check(_lib.lib.stokesmg_set_local_solver(self._h, {"exact": 0, "mlp": 1}[solver], self._mode(mode)))
+    def set_local_solver(self, solver="exact", mode="bf16", damping=1.0):
+        self._check(_lib.lib.stokesmg_set_local_solver(self._h, {"exact": 0, "mlp": 1}[solver], self._mode(mode),
+                                                       float(damping)))
 
     def set_fallback(self, rho_ref):
         self._check(_lib.lib.stokesmg_set_fallback(self._h, float(rho_ref)))

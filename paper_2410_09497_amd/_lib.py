@@ -48,6 +48,7 @@ def _load():
         "stokesmg_solve_workspace_size": (i32, [vp, i32, szp]),
         "solve": (i32, [vp, vp, vp, ctypes.c_double, i32, i32, i32, vp, ctypes.c_size_t, ctypes.POINTER(Info), vp]),
         "stokesmg_rhs_manufactured": (i32, [vp, i32, i32, vp, vp]),
+        "stokesmg_rhs_fourier": (i32, [vp, i32, i32, vp, vp, vp, vp, vp]),
         "mlp_dims": (i32, [vp, i64p, i64p]),
         "mlp_workspace_size": (i32, [vp, ctypes.c_int64, szp]),
         "mlp_set_workspace": (i32, [vp, vp, ctypes.c_size_t, ctypes.c_int64]),
@@ -60,7 +61,7 @@ def _load():
         "mlp_collect_pairs": (i32, [vp, vp, vp, vp, vp, ctypes.c_int64, i64p, vp]),
         "mlp_train": (i32, [vp, i32, vp, vp, ctypes.c_int64, i32, i32, ctypes.c_float, ctypes.c_uint64,
                             ctypes.POINTER(ctypes.c_float), vp]),
-        "stokesmg_set_local_solver": (i32, [vp, i32, i32]),
+        "stokesmg_set_local_solver": (i32, [vp, i32, i32, ctypes.c_double]),
         "stokesmg_set_fallback": (i32, [vp, ctypes.c_double]),
     }
     for name, (res, args) in sig.items():
@@ -75,6 +76,6 @@ lib = _load()
 EXPORTED = ["stokesmg_create", "stokesmg_destroy", "stokesmg_last_error", "stokesmg_num_levels",
             "stokesmg_sizes", "stokesmg_workspace_size", "stokesmg_set_workspace", "stokes_apply",
             "stokes_residual", "patch_smooth", "stokesmg_cg_stats", "vcycle", "stokesmg_solve_workspace_size",
-            "solve", "stokesmg_rhs_manufactured", "mlp_dims", "mlp_workspace_size", "mlp_set_workspace", "mlp_init",
+            "solve", "stokesmg_rhs_manufactured", "stokesmg_rhs_fourier", "mlp_dims", "mlp_workspace_size", "mlp_set_workspace", "mlp_init",
             "mlp_get_state", "mlp_set_state", "mlp_forward", "mlp_backward", "mlp_adam_step", "mlp_collect_pairs",
             "mlp_train", "stokesmg_set_local_solver", "stokesmg_set_fallback"]

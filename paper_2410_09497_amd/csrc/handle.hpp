@@ -60,6 +60,7 @@ struct stokesmg {
     } mlp;
     int local_solver = STOKESMG_LOCAL_EXACT;
     int mlp_mode = STOKESMG_MLP_BF16;
+    double mlp_omega = 1.0;                  // damping of the learned corrections
     double rho_ref = 0.0;
 
     int fail(int code, const std::string& msg) {

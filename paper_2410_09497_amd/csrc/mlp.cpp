@@ -174,7 +174,7 @@ int mlp_interior_solve(stokesmg* h, int level, bool f64, void* x, const void* r,
         const int cnt = int(std::min<int64_t>(m.rows, np - p0));
         SMG_HIP(h, launch_patch_gather(f64, r, n, k, colour, int(p0), cnt, X, m.d, s, st));
         if (int rc = forward(h, bf16, X, nullptr, cnt, Y, false, st)) return rc;
-        SMG_HIP(h, launch_patch_scatter(f64, x, n, k, colour, int(p0), cnt, Y, m.d, s, st));
+        SMG_HIP(h, launch_patch_scatter(f64, x, n, k, colour, int(p0), cnt, Y, m.d, s, h->mlp_omega, st));
     }
     return STOKESMG_OK;
 }
@@ -395,8 +395,9 @@ int mlp_collect_pairs(stokesmg_t* h, const double* b, double* x, float* X, float
     return smg::vcycle_run(h, true, b, x, static_cast<hipStream_t>(stream), &c);
 }
 
-int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode) {
+int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode, double mlp_damping) {
     if (!h) return STOKESMG_EINVAL;
+    if (!(mlp_damping > 0.0 && mlp_damping <= 1.0)) return h->fail(STOKESMG_EINVAL, "mlp_damping must be in (0, 1]");
     if (local_solver != STOKESMG_LOCAL_EXACT && local_solver != STOKESMG_LOCAL_MLP)
         return h->fail(STOKESMG_EINVAL, "unknown local solver");
     if (int rc = check_mode(h, mlp_mode)) return rc;
@@ -404,6 +405,7 @@ int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode) {
         if (int rc = check_mlp(h, true)) return rc;
     h->local_solver = local_solver;
     h->mlp_mode = mlp_mode;
+    h->mlp_omega = mlp_damping;
     return STOKESMG_OK;
 }
 

@@ -476,16 +476,22 @@ __global__ void __launch_bounds__(256) patch_gather_kernel(const T* __restrict__
 template <typename T>
 __global__ void __launch_bounds__(256) patch_scatter_kernel(T* __restrict__ x, PatchGeo g, int p0,
                                                             const float* __restrict__ Y, int ldy,
-                                                            const float* __restrict__ s) {
+                                                            const float* __restrict__ s, double omega) {
+    __shared__ double red[256];
     int v[3];
     patch_vertex(g, p0 + blockIdx.x, v);
-    const float sc = s[blockIdx.x];
-    if (sc == 0.0f) return;
+    const double sc = omega * double(s[blockIdx.x]);
+    if (sc == 0.0) return;   // uniform over the workgroup: no barrier reached yet
     const float* row = Y + size_t(blockIdx.x) * ldy;
+    // the exact correction K_j^+ R_j r has zero coefficient mean in the patch
+    // pressure (it is orthogonal to the kernel of K_j): project the learned one
+    double ps = 0.0;
+    for (int q = 3 * g.nvel + threadIdx.x; q < g.size; q += 256) ps += row[q];
+    const double pmean = block_sum(ps, red) / double(g.size - 3 * g.nvel);
     for (int q = threadIdx.x; q < g.size; q += 256) {
         bool pres;
         const size_t gi = patch_index(g, v, q, pres);
-        const double val = double(sc) * row[q] * (pres ? double(g.n) : 1.0);
+        const double val = pres ? sc * (row[q] - pmean) * double(g.n) : sc * row[q];
         x[gi] = T(double(x[gi]) + val);
     }
 }
@@ -521,13 +527,13 @@ hipError_t launch_patch_gather(bool f64, const void* r, int n, int k, int colour
 }
 
 hipError_t launch_patch_scatter(bool f64, void* x, int n, int k, int colour, int p0, int np, const float* Y, int ldy,
-                                const float* s, hipStream_t st) {
+                                const float* s, double omega, hipStream_t st) {
     const PatchGeo g = make_geo(n, k, colour);
     if (np <= 0) return hipSuccess;
     if (f64) hipLaunchKernelGGL(patch_scatter_kernel<double>, dim3(np), dim3(256), 0, st, static_cast<double*>(x), g,
-                                p0, Y, ldy, s);
+                                p0, Y, ldy, s, omega);
     else hipLaunchKernelGGL(patch_scatter_kernel<float>, dim3(np), dim3(256), 0, st, static_cast<float*>(x), g, p0,
-                            Y, ldy, s);
+                            Y, ldy, s, omega);
     return hipGetLastError();
 }
 

@@ -53,14 +53,14 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, f
 // level vector (row q of X / Y / T belongs to patch p0 + q).
 //   gather:  X[q] = (R_j r scaled by 1/h (velocity) and 1/h^2 (pressure)) / s_q,
 //            s_q = its Euclidean norm (X[q] = 0 and s_q = 0 for a zero residual)
-//   scatter: x[R_j] += s_q (Y[q] velocity rows, Y[q] pressure rows / h)
+//   scatter: x[R_j] += omega s_q (Y[q] velocity rows, (Y[q] pressure rows - their mean) / h)
 //   gather_diff (pair capture): T[q] = (x_new - x_old)[R_j] scaled to (U, h P) / s_q
 // Patches of a colour are its interior vertices in lexicographic order (x
 // fastest).  The level vectors are double (f64) or float.
 hipError_t launch_patch_gather(bool f64, const void* r, int n, int k, int colour, int p0, int np, float* X, int ldx,
                                float* s, hipStream_t st);
 hipError_t launch_patch_scatter(bool f64, void* x, int n, int k, int colour, int p0, int np, const float* Y, int ldy,
-                                const float* s, hipStream_t st);
+                                const float* s, double omega, hipStream_t st);
 hipError_t launch_patch_gather_diff(bool f64, const void* xnew, const void* xold, int n, int k, int colour, int p0,
                                     int np, float* T, int ldt, const float* s, hipStream_t st);
 

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "apply.hpp"
@@ -93,8 +94,8 @@ struct Term {       // coef * g0(x) g1(y) g2(z)
 // 1D load vectors of function g against the basis of one direction kind on n cells:
 // value[position] = int g phi_position (Gauss with k+2 points per cell), and the
 // boundary vector bnd[position] = sum over the two ends s of g(s) (2 gamma phi(s) - n_s phi'(s))
-void load_1d(const smg::Ref1D& r, int n, bool cont, int g, double gamma, std::vector<double>& val,
-             std::vector<double>& bnd) {
+void load_1d(const smg::Ref1D& r, int n, bool cont, const std::function<double(double)>& g, double gamma,
+             std::vector<double>& val, std::vector<double>& bnd) {
     const int k = r.k, m = k + 1, N1 = n * m;
     const double h = 1.0 / n;
     std::vector<double> xq, wq;
@@ -105,19 +106,19 @@ void load_1d(const smg::Ref1D& r, int n, bool cont, int g, double gamma, std::ve
         for (int c = 0; c < n; ++c)
             for (int a = 0; a < m; ++a) {
                 double s = 0.0;
-                for (size_t q = 0; q < xq.size(); ++q) s += wq[q] * h * fn(g, (c + xq[q]) * h) * smg::lagrange(r.xg, a, xq[q]);
+                for (size_t q = 0; q < xq.size(); ++q) s += wq[q] * h * g((c + xq[q]) * h) * smg::lagrange(r.xg, a, xq[q]);
                 val[c * m + a] = s;
             }
         for (int a = 0; a < m; ++a) {
-            bnd[a] += fn(g, 0.0) * (2.0 * gamma * r.eL[a] + r.dL[a] / h);                // n = -1: -n phi' = +phi'
-            bnd[(n - 1) * m + a] += fn(g, 1.0) * (2.0 * gamma * r.eR[a] - r.dR[a] / h);
+            bnd[a] += g(0.0) * (2.0 * gamma * r.eL[a] + r.dL[a] / h);                // n = -1: -n phi' = +phi'
+            bnd[(n - 1) * m + a] += g(1.0) * (2.0 * gamma * r.eR[a] - r.dR[a] / h);
         }
     } else {
         std::vector<double> full(N1 + 1, 0.0), fb(N1 + 1, 0.0);
         for (int c = 0; c < n; ++c)
             for (int b = 0; b <= m; ++b) {
                 double s = 0.0;
-                for (size_t q = 0; q < xq.size(); ++q) s += wq[q] * h * fn(g, (c + xq[q]) * h) * smg::lagrange(r.xl, b, xq[q]);
+                for (size_t q = 0; q < xq.size(); ++q) s += wq[q] * h * g((c + xq[q]) * h) * smg::lagrange(r.xl, b, xq[q]);
                 full[c * m + b] += s;
             }
         val.assign(full.begin() + 1, full.end() - 1);   // interior nodes only
@@ -255,9 +256,19 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
             SMG_HIP(h, hipMemcpyAsync(coef, h2.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, st));
             SMG_HIP(h, smg::launch_multiaxpy(V, N, coef, j + 1, -1.0, 1.0, w, N, st));
             SMG_HIP(h, hipStreamSynchronize(st));
-            for (int i = 0; i <= j; ++i) H[size_t(i) * restart + j] = hv[i] + h2[i];
             double hn = 0.0;
             if (int rc = host_dots(h, w, 0, w, 1, N, &hn, st)) return rc;
+            bool finite = std::isfinite(hn);
+            for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(hv[i]) && std::isfinite(h2[i]);
+            if (!finite) {
+                if (h->local_solver != STOKESMG_LOCAL_MLP)
+                    return h->fail(STOKESMG_EHIP, "non-finite values in the preconditioned Krylov vector");
+                // a non-finite learned correction: drop this step, restart with the exact local solver
+                h->local_solver = STOKESMG_LOCAL_EXACT;
+                fallback_at = it;
+                break;
+            }
+            for (int i = 0; i <= j; ++i) H[size_t(i) * restart + j] = hv[i] + h2[i];
             hn = std::sqrt(hn);
             H[size_t(j + 1) * restart + j] = hn;
             double* vn = V + size_t(j + 1) * N;
@@ -282,15 +293,19 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
             hist.push_back(std::fabs(g[j + 1]) / bnorm);
             if (h->local_solver == STOKESMG_LOCAL_MLP) {
                 const double rho = hist[hist.size() - 1] / hist[hist.size() - 2];
-                const bool bad = rho > 1.0 || (h->rho_ref > 0.0 && rho > std::max(2.0 * h->rho_ref, 1e-3));
-                if (bad) {
+                const double bound = h->rho_ref > 0.0 ? std::max(2.0 * h->rho_ref, 1e-3) : 1.0;
+                if (!(rho < bound)) {   // also catches NaN
+                    // keep this step, then restart: the Krylov directions of the learned
+                    // steps would slow the exact ones down
                     h->local_solver = STOKESMG_LOCAL_EXACT;
                     fallback_at = it;
+                    break;
                 }
             }
             if (hist.back() <= rtol || it >= max_it) break;
         }
         // x += Z y, H(0:j, 0:j) y = g(0:j)
+        if (jdone == 0) continue;
         std::vector<double> y(jdone);
         for (int i = jdone - 1; i >= 0; --i) {
             double s = g[i];
@@ -361,19 +376,68 @@ int stokesmg_rhs_manufactured(stokesmg_t* h, int level, int problem, double* b, 
         };
         for (const auto& t : f[c]) {
             std::vector<double> v[3], bd[3];
-            for (int d = 0; d < 3; ++d) load_1d(ref, n, d == c, t.g[d], lv.gamma, v[d], bd[d]);
+            for (int d = 0; d < 3; ++d) load_1d(ref, n, d == c, [&](double x) { return fn(t.g[d], x); }, lv.gamma, v[d], bd[d]);
             add(t.c, v[0], v[1], v[2]);
         }
         // boundary (Nitsche) terms of the tangential data: faces normal to d != c
         for (const auto& t : u[c]) {
             std::vector<double> v[3], bd[3];
-            for (int d = 0; d < 3; ++d) load_1d(ref, n, d == c, t.g[d], lv.gamma, v[d], bd[d]);
+            for (int d = 0; d < 3; ++d) load_1d(ref, n, d == c, [&](double x) { return fn(t.g[d], x); }, lv.gamma, v[d], bd[d]);
             for (int d = 0; d < 3; ++d) {
                 if (d == c) continue;
                 // face integral: the other two directions by quadrature, direction d by the end values
                 std::vector<double> a[3] = {v[0], v[1], v[2]};
                 a[d] = bd[d];
                 add(t.c, a[0], a[1], a[2]);
+            }
+        }
+    }
+    SMG_HIP(h, hipMemcpyAsync(b, out.data(), out.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    SMG_HIP(h, hipStreamSynchronize(st));
+    return STOKESMG_OK;
+}
+
+int stokesmg_rhs_fourier(stokesmg_t* h, int level, int n_modes, const int* kappa, const double* amp,
+                         const double* theta, double* b, void* stream) {
+    if (!h) return STOKESMG_EINVAL;
+    if (level < 0 || level >= h->n_levels || !b) return h->fail(STOKESMG_EINVAL, "bad level or null vector");
+    if (n_modes < 0 || (n_modes > 0 && (!kappa || !amp || !theta)))
+        return h->fail(STOKESMG_EINVAL, "bad mode arrays");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const auto& lv = h->lv[level];
+    const int n = lv.n, N1 = lv.N1;
+    smg::Ref1D ref(h->cfg.k);
+    std::vector<double> out(size_t(level_total(h, level)), 0.0);
+    const size_t nc = size_t(N1 - 1) * N1 * N1;
+    // cos(A + B + C + theta) with A = pi k0 x, B = pi k1 y, C = pi k2 z, expanded into the
+    // eight separable products of cosines and sines of A, B, C
+    for (int c = 0; c < 3; ++c) {
+        const int ext[3] = {c == 0 ? N1 - 1 : N1, c == 1 ? N1 - 1 : N1, c == 2 ? N1 - 1 : N1};
+        for (int m = 0; m < n_modes; ++m) {
+            const int* kp = kappa + (size_t(c) * n_modes + m) * 3;
+            const double a = amp[size_t(c) * n_modes + m], th = theta[size_t(c) * n_modes + m];
+            std::vector<double> vc[3], vs[3], bd;
+            for (int d = 0; d < 3; ++d) {
+                const double w = M_PI * kp[d];
+                load_1d(ref, n, d == c, [w](double x) { return std::cos(w * x); }, lv.gamma, vc[d], bd);
+                load_1d(ref, n, d == c, [w](double x) { return std::sin(w * x); }, lv.gamma, vs[d], bd);
+            }
+            const double ct = a * std::cos(th), stt = a * std::sin(th);
+            // (sA, sB, sC) selects sine factors; cos(phi) and sin(phi) coefficients of each product
+            for (int sel = 0; sel < 8; ++sel) {
+                const int ns = (sel & 1) + ((sel >> 1) & 1) + ((sel >> 2) & 1);
+                // cos(phi) = sum over even ns of (-1)^(ns/2) prod; sin(phi) = sum over odd ns of (-1)^((ns-1)/2) prod
+                const double coef = (ns % 2 == 0) ? ct * ((ns / 2) % 2 ? -1.0 : 1.0)
+                                                  : -stt * (((ns - 1) / 2) % 2 ? -1.0 : 1.0);
+                const std::vector<double>& a0 = (sel & 1) ? vs[0] : vc[0];
+                const std::vector<double>& a1 = (sel & 2) ? vs[1] : vc[1];
+                const std::vector<double>& a2 = (sel & 4) ? vs[2] : vc[2];
+                for (int Zi = 0; Zi < ext[2]; ++Zi)
+                    for (int Yi = 0; Yi < ext[1]; ++Yi) {
+                        const double sc = coef * a1[Yi] * a2[Zi];
+                        double* row = out.data() + size_t(c) * nc + size_t(ext[0]) * (Yi + size_t(ext[1]) * Zi);
+                        for (int Xi = 0; Xi < ext[0]; ++Xi) row[Xi] += sc * a0[Xi];
+                    }
             }
         }
     }

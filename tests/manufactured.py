@@ -59,3 +59,21 @@ def ponly_p(x, y, z):
 
 def ponly_f(x, y, z):
     return np.array([2 * (x - 0.5) * (y - 0.5), (x - 0.5) ** 2 + 0.0 * y, 0.0 * z])
+
+
+def fourier_force(seed, n_modes=8):
+    """The random smooth force of synth.fourier_modes(seed), evaluated
+    pointwise: f_c = sum_m a cos(pi kappa . x + theta)."""
+    from paper_2410_09497_amd.synth import fourier_modes
+    kappa, amp, theta = fourier_modes(seed, n_modes=n_modes)
+
+    def f(x, y, z):
+        out = []
+        for c in range(3):
+            v = np.zeros_like(np.asarray(x, dtype=float))
+            for m in range(n_modes):
+                kx, ky, kz = kappa[c, m]
+                v = v + amp[c, m] * np.cos(np.pi * (kx * x + ky * y + kz * z) + theta[c, m])
+            out.append(v)
+        return np.array(out)
+    return f

@@ -55,6 +55,19 @@ def test_rhs_manufactured(n, k):
     assert rel_err(b, bref) <= 1e-12
 
 
+@pytest.mark.parametrize("n,k,seed", [(2, 1, 0), (4, 2, 5), (8, 1, 7)])
+def test_rhs_fourier(n, k, seed):
+    """Random smooth force: the library's separable expansion against the
+    oracle's pointwise quadrature of the same field."""
+    torch = need_gpu()
+    S = Stokes(n, k)
+    bref = S.rhs(mf.fourier_force(seed))
+    announce("rhs fourier", f"n={n} k={k} seed={seed}")
+    mg = StokesMG(n, k, n_levels=1)
+    b = mg.rhs_fourier(seed).cpu().numpy()
+    assert rel_err(b, bref) <= 1e-12
+
+
 @pytest.mark.parametrize("n,k", [(4, 1), (8, 1), (4, 2)])
 def test_fgmres_history_matches_oracle(n, k):
     torch = need_gpu()
