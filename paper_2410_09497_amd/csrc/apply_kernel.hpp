@@ -45,12 +45,16 @@ __device__ inline int xcd_remap(int bid, int G) {
     return xcd * per + (xcd < extra ? xcd : extra) + local;
 }
 
-template <int K, typename T, int CX, int CY, bool RESID>
+// PF: the next plane's global loads are issued into registers before the
+// current plane is computed (software pipelining), and stored to LDS at the
+// start of the next plane; otherwise each plane is loaded, then computed.
+template <int K, typename T, int CX, int CY, bool RESID, bool PF>
 __global__ void __launch_bounds__(CX * CY * (K + 1) * (K + 1))
 stokes_apply_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T* __restrict__ y,
                     const T* __restrict__ tab, int n, int cz, int tiles_x, int tiles_y) {
     using S = ApplyShape<K, CX, CY>;
     constexpr int M = S::M, TX = S::TX, TY = S::TY, NT = S::NT, RX = S::RX, RY = S::RY, RS = S::RS;
+    constexpr int NL = (RS + NT - 1) / NT;   // plane elements per thread and field
     using TB = Tab<K>;
 
     __shared__ T s_tab[TB::size];
@@ -98,6 +102,31 @@ stokes_apply_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T* __re
     const T* __restrict__ MD = s_tab + TB::MDg;
     const T mda = MD[a], mdb = MD[b];
 
+    // plane Z of the four fields, tile + halo, zero outside the domain
+    auto load_plane = [&](int Z, T (&v)[4][NL]) {
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int i = tid + t * NT;
+            const int gxp = X0 - M + i % RX, gyp = Y0 - M + i / RX;
+            const bool in = i < RS && gxp >= 0 && gxp < N1 && gyp >= 0 && gyp < N1;
+            T vux = 0, vuy = 0, vuz = 0, vp = 0;
+            if (in) {
+                if (gxp < N1 - 1) vux = gx[gxp + size_t(N1 - 1) * (gyp + size_t(N1) * Z)];
+                if (gyp < N1 - 1) vuy = gy[gxp + size_t(N1) * (gyp + size_t(N1 - 1) * Z)];
+                if (Z < N1 - 1) vuz = gz[gxp + size_t(N1) * (gyp + size_t(N1) * Z)];
+                vp = gp[gxp + size_t(N1) * (gyp + size_t(N1) * Z)];
+            }
+            v[0][t] = vux;
+            v[1][t] = vuy;
+            v[2][t] = vuz;
+            v[3][t] = vp;
+        }
+    };
+    T pf[4][NL];
+    const int Zfirst = (L0 > 0 ? L0 - 1 : 0) * M;
+    const int Zlast = (L1 < n ? L1 + 1 : n) * M - 1;
+    if constexpr (PF) load_plane(Zfirst, pf);
+
     int buf = 0;
     for (int Lin = L0 - 1; Lin <= L1; ++Lin) {
         const bool have = (Lin >= 0) && (Lin < n);
@@ -107,21 +136,28 @@ stokes_apply_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T* __re
             if (have) {
                 const int Z = Lin * M + c;
                 T* su = &s_u[buf][0][0];
-                // 1) plane Z of the four fields, tile + halo, zero outside the domain
-                for (int i = tid; i < RS; i += NT) {
-                    const int gxp = X0 - M + i % RX, gyp = Y0 - M + i / RX;
-                    const bool inx = gxp >= 0 && gxp < N1, iny = gyp >= 0 && gyp < N1;
-                    T vux = 0, vuy = 0, vuz = 0, vp = 0;
-                    if (inx && iny) {
-                        if (gxp < N1 - 1) vux = gx[gxp + size_t(N1 - 1) * (gyp + size_t(N1) * Z)];
-                        if (gyp < N1 - 1) vuy = gy[gxp + size_t(N1) * (gyp + size_t(N1 - 1) * Z)];
-                        if (Z < N1 - 1) vuz = gz[gxp + size_t(N1) * (gyp + size_t(N1) * Z)];
-                        vp = gp[gxp + size_t(N1) * (gyp + size_t(N1) * Z)];
+                // 1) plane Z of the four fields into LDS
+                if constexpr (PF) {
+#pragma unroll
+                    for (int t = 0; t < NL; ++t) {
+                        const int i = tid + t * NT;
+                        if (i < RS) {
+#pragma unroll
+                            for (int f = 0; f < 4; ++f) su[f * RS + i] = pf[f][t];
+                        }
                     }
-                    su[0 * RS + i] = vux;
-                    su[1 * RS + i] = vuy;
-                    su[2 * RS + i] = vuz;
-                    su[3 * RS + i] = vp;
+                    if (Z < Zlast) load_plane(Z + 1, pf);   // in flight during this plane's work
+                } else {
+                    T v[4][NL];
+                    load_plane(Z, v);
+#pragma unroll
+                    for (int t = 0; t < NL; ++t) {
+                        const int i = tid + t * NT;
+                        if (i < RS) {
+#pragma unroll
+                            for (int f = 0; f < 4; ++f) su[f * RS + i] = v[f][t];
+                        }
+                    }
                 }
                 __syncthreads();
                 const T* sux = su;
