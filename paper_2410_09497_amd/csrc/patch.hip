@@ -1,6 +1,8 @@
 // Launcher of the vertex-patch local solves (one workgroup per patch of a colour).
 #include "patch.hpp"
 
+#include <cstdlib>
+
 #include "patch_kernel.hpp"
 
 namespace smg {
@@ -13,17 +15,39 @@ int count_parity(int n, int parity) {
     return (n - 1 >= first) ? (n - 1 - first) / 2 + 1 : 0;
 }
 
-template <int K, typename T>
-hipError_t launch(void* x, const void* r, const void* ptab, int n, int colour, double rtol, int maxit, int* counters,
-                  bool bonly, hipStream_t st) {
+template <int K, typename T, int NTP>
+hipError_t launch_nt(void* x, const void* r, const void* ptab, int n, int colour, double rtol, int maxit,
+                     int* counters, bool bonly, hipStream_t st) {
     const int cx = count_parity(n, colour & 1), cy = count_parity(n, (colour >> 1) & 1),
               cz = count_parity(n, (colour >> 2) & 1);
     const int grid = cx * cy * cz;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((patch_solve_kernel<K, T>), dim3(grid), dim3(PatchShape<K>::NT), 0, st, static_cast<T*>(x),
+    hipLaunchKernelGGL((patch_solve_kernel<K, T, NTP>), dim3(grid), dim3(PatchShape<K, NTP>::NT), 0, st,
+                       static_cast<T*>(x),
                        static_cast<const T*>(r), static_cast<const T*>(ptab), n, colour, cx, cy, T(rtol), maxit,
                        counters, int(bonly));
     return hipGetLastError();
+}
+
+// threads per patch: the degree's default (PatchShape), or STOKESMG_PATCH_THREADS = 64 | 128 | 256
+// for comparison runs
+template <int K, typename T>
+hipError_t launch(void* x, const void* r, const void* ptab, int n, int colour, double rtol, int maxit, int* counters,
+                  bool bonly, hipStream_t st) {
+    static const int threads = [] {
+        const char* s = std::getenv("STOKESMG_PATCH_THREADS");
+        return s ? std::atoi(s) : 0;
+    }();
+    switch (threads) {
+        case 64: return launch_nt<K, T, 64>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
+        case 128: return launch_nt<K, T, 128>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
+        case 256: return launch_nt<K, T, 256>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
+        default: {
+            // measured: two waves for FP32 at k = 3, four for FP64 at k = 2, else PatchShape's default
+            constexpr int def = (K == 3 && sizeof(T) == 4) ? 128 : ((K == 2 && sizeof(T) == 8) ? 256 : 0);
+            return launch_nt<K, T, def>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
+        }
+    }
 }
 
 }  // namespace

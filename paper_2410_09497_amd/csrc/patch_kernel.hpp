@@ -20,14 +20,42 @@
 
 namespace smg {
 
-template <int K>
+// threads per patch: NT_OVERRIDE if positive, else by degree (measured on
+// MI355X: one wave for k = 1, two for k = 2, four for k = 3; the launcher
+// picks two for FP32 at k = 3)
+template <int K, int NT_OVERRIDE = 0>
 struct PatchShape {
     static constexpr int M = K + 1;
     static constexpr int NC = 2 * K + 1, ND = 2 * K + 2;
     static constexpr int NV = NC * ND * ND;      // one velocity component
     static constexpr int NP = ND * ND * ND;      // pressure
-    static constexpr int NT = 256;
+    static constexpr int NT = NT_OVERRIDE > 0 ? NT_OVERRIDE : (K == 1 ? 64 : (K == 2 ? 128 : 256));
+    static constexpr int NW = NT / 64;           // waves
 };
+
+// (i0, i1, i2) of entry e of velocity component c: the extents depend on c
+// (2k+1 in its own direction, 2k+2 in the others), so branch on c and keep
+// every divisor a compile-time constant
+template <int K>
+__device__ inline void vel_coords(int c, int e, int& i0, int& i1, int& i2) {
+    constexpr int NC = 2 * K + 1, ND = 2 * K + 2;
+    if (c == 0) {
+        i0 = e % NC;
+        const int t = e / NC;
+        i1 = t % ND;
+        i2 = t / ND;
+    } else if (c == 1) {
+        i0 = e % ND;
+        const int t = e / ND;
+        i1 = t % NC;
+        i2 = t / NC;
+    } else {
+        i0 = e % ND;
+        const int t = e / ND;
+        i1 = t % ND;
+        i2 = t / ND;
+    }
+}
 
 // extents (x fastest) of component c: the continuous direction is c
 template <int K>
@@ -35,30 +63,58 @@ __device__ constexpr int ext(int c, int d) {
     return d == c ? 2 * K + 1 : 2 * K + 2;
 }
 
-// block-wide sum of one value per thread (NT = 256: four waves)
-template <typename T>
+// block-wide sums of one or two values per thread (NW waves; red holds 2 NW)
+template <int NW, typename T>
 __device__ inline T block_sum(T v, T* red) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if constexpr (NW == 1) return v;
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) s += red[i];
+    return s;
+}
+template <int NW, typename T>
+__device__ inline void block_sum2(T& a, T& b, T* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if constexpr (NW == 1) return;
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        red[w] = a;
+        red[NW + w] = b;
+    }
+    __syncthreads();
+    a = 0;
+    b = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        a += red[i];
+        b += red[NW + i];
+    }
 }
 
 // out[comp] = contraction of in[comp] along direction d with matrix
 // S_(comp, d) (transposed if TR), for the three velocity components at once.
-template <int K, typename T, bool TR>
+template <int K, int NTP, typename T, bool TR>
 __device__ inline void contract3(const T* in, T* out, int d, const T* const* Sdir) {
-    using P = PatchShape<K>;
-    constexpr int NV = P::NV;
+    using P = PatchShape<K, NTP>;
+    constexpr int NV = P::NV, NC = P::NC, ND = P::ND;
     for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
         const int c = idx / NV, e = idx - c * NV;
-        const int e0 = ext<K>(c, 0), e1 = ext<K>(c, 1), e2 = ext<K>(c, 2);
-        const int i0 = e % e0, t = e / e0, i1 = t % e1, i2 = t / e1;
-        const int nd = d == 0 ? e0 : (d == 1 ? e1 : e2);
-        const int ii = d == 0 ? i0 : (d == 1 ? i1 : i2);
+        int i[3];
+        vel_coords<K>(c, e, i[0], i[1], i[2]);
+        const int e0 = c == 0 ? NC : ND, e1 = c == 1 ? NC : ND;
+        const int ii = i[d];
+        const int nd = d == c ? NC : ND;
         const int st = d == 0 ? 1 : (d == 1 ? e0 : e0 * e1);
         const T* base = in + c * NV + e - ii * st;
         const T* S = Sdir[c * 3 + d];
@@ -68,62 +124,136 @@ __device__ inline void contract3(const T* in, T* out, int d, const T* const* Sdi
     }
 }
 
-// v <- A^{-1} v for the three components (in place), work buffers w1, w2
-template <int K, typename T>
-__device__ inline void fd_inverse(T* v, T* w1, T* w2, const T* const* Sdir, const T* const* Ldir) {
-    using P = PatchShape<K>;
+// Line form of contract3 along direction D: one thread per 1D line of a
+// component's box (the line along D through fixed indices of the two other
+// directions).  The thread loads the line once into registers and writes the
+// whole contracted line: n reads and n writes per line instead of n^2 reads.
+template <int K, int NTP, typename T, bool TR, int D>
+__device__ inline void contract_lines(const T* in, T* out, const T* const* Sdir) {
+    using P = PatchShape<K, NTP>;
+    constexpr int NV = P::NV, NC = P::NC, ND = P::ND;
+    // lines per component: NV / (extent along D); the component whose continuous direction is D has NC
+    constexpr int LC = NV / NC, LD = NV / ND;
+    constexpr int L0 = D == 0 ? LC : LD, L1 = D == 1 ? LC : LD, L2 = D == 2 ? LC : LD;
+    for (int l = threadIdx.x; l < L0 + L1 + L2; l += P::NT) {
+        const int c = l < L0 ? 0 : (l < L0 + L1 ? 1 : 2);
+        const int lc = l - (c == 0 ? 0 : (c == 1 ? L0 : L0 + L1));
+        const int e0 = c == 0 ? NC : ND, e1 = c == 1 ? NC : ND;
+        int base, st;
+        if constexpr (D == 0) {
+            base = lc * e0;            // (i1, i2) -> i1 e0 + i2 e0 e1 = lc e0
+            st = 1;
+        } else if constexpr (D == 1) {
+            const int i0 = lc % e0, i2 = lc / e0;
+            base = i0 + i2 * e0 * e1;
+            st = e0;
+        } else {
+            base = lc;                 // (i0, i1) -> i0 + i1 e0 = lc
+            st = e0 * e1;
+        }
+        const T* src = in + c * NV + base;
+        T* dst = out + c * NV + base;
+        const T* S = Sdir[c * 3 + D];
+        if (c == D) {
+            T v[NC];
+#pragma unroll
+            for (int j = 0; j < NC; ++j) v[j] = src[j * st];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                T acc = 0;
+#pragma unroll
+                for (int j = 0; j < NC; ++j) acc += (TR ? S[j * NC + i] : S[i * NC + j]) * v[j];
+                dst[i * st] = acc;
+            }
+        } else {
+            T v[ND];
+#pragma unroll
+            for (int j = 0; j < ND; ++j) v[j] = src[j * st];
+#pragma unroll
+            for (int i = 0; i < ND; ++i) {
+                T acc = 0;
+#pragma unroll
+                for (int j = 0; j < ND; ++j) acc += (TR ? S[j * ND + i] : S[i * ND + j]) * v[j];
+                dst[i * st] = acc;
+            }
+        }
+    }
+}
+
+// v <- A^{-1} v for the three components (in place), work buffer w
+template <int K, int NTP, typename T>
+__device__ inline void fd_inverse(T* v, T* w, const T* const* Sdir, const T* const* Ldir) {
+    using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV;
-    contract3<K, T, true>(v, w1, 0, Sdir);
-    __syncthreads();
-    contract3<K, T, true>(w1, w2, 1, Sdir);
-    __syncthreads();
-    contract3<K, T, true>(w2, w1, 2, Sdir);
+    // FP32: a thread per line (fewer LDS reads); FP64: a thread per entry, whose
+    // lanes read with unit stride (the lines' strided FP64 reads conflict in the
+    // LDS banks and measured slower)
+    if constexpr (sizeof(T) == 8) {
+        contract3<K, NTP, T, true>(v, w, 0, Sdir);
+        __syncthreads();
+        contract3<K, NTP, T, true>(w, v, 1, Sdir);
+        __syncthreads();
+        contract3<K, NTP, T, true>(v, w, 2, Sdir);
+    } else {
+        contract_lines<K, NTP, T, true, 0>(v, w, Sdir);
+        __syncthreads();
+        contract_lines<K, NTP, T, true, 1>(w, v, Sdir);
+        __syncthreads();
+        contract_lines<K, NTP, T, true, 2>(v, w, Sdir);
+    }
     __syncthreads();
     for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
         const int c = idx / NV, e = idx - c * NV;
-        const int e0 = ext<K>(c, 0), e1 = ext<K>(c, 1);
-        const int i0 = e % e0, t = e / e0, i1 = t % e1, i2 = t / e1;
-        w1[idx] /= Ldir[c * 3 + 0][i0] + Ldir[c * 3 + 1][i1] + Ldir[c * 3 + 2][i2];
+        int i0, i1, i2;
+        vel_coords<K>(c, e, i0, i1, i2);
+        w[idx] /= Ldir[c * 3 + 0][i0] + Ldir[c * 3 + 1][i1] + Ldir[c * 3 + 2][i2];
     }
     __syncthreads();
-    contract3<K, T, false>(w1, w2, 2, Sdir);
-    __syncthreads();
-    contract3<K, T, false>(w2, w1, 1, Sdir);
-    __syncthreads();
-    contract3<K, T, false>(w1, v, 0, Sdir);
+    if constexpr (sizeof(T) == 8) {
+        contract3<K, NTP, T, false>(w, v, 2, Sdir);
+        __syncthreads();
+        contract3<K, NTP, T, false>(v, w, 1, Sdir);
+        __syncthreads();
+        contract3<K, NTP, T, false>(w, v, 0, Sdir);
+    } else {
+        contract_lines<K, NTP, T, false, 2>(w, v, Sdir);
+        __syncthreads();
+        contract_lines<K, NTP, T, false, 1>(v, w, Sdir);
+        __syncthreads();
+        contract_lines<K, NTP, T, false, 0>(w, v, Sdir);
+    }
     __syncthreads();
 }
 
 // vel = B^T p:  (B^T p)_c[i] = -D^T along c times the DG masses of the other directions
-template <int K, typename T>
+template <int K, int NTP, typename T>
 __device__ inline void apply_BT(const T* p, T* vel, const T* Dp, const T* md) {
-    using P = PatchShape<K>;
+    using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV, NC = P::NC, ND = P::ND;
     for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
         const int c = idx / NV, e = idx - c * NV;
-        const int e0 = ext<K>(c, 0), e1 = ext<K>(c, 1);
-        const int i[3] = {e % e0, (e / e0) % e1, e / (e0 * e1)};
+        int i0, i1, i2;
+        vel_coords<K>(c, e, i0, i1, i2);
         // pressure index equals i in the DG directions; the continuous one is summed
-        int ps[3] = {1, ND, ND * ND};
-        int pbase = 0;
-        T mass = 1;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            if (d != c) {
-                pbase += i[d] * ps[d];
-                mass *= md[i[d]];
-            }
-        const int ic = i[c];
+        int pbase, pst, ic;
+        T mass;
+        if (c == 0) {
+            pbase = ND * (i1 + ND * i2), pst = 1, ic = i0, mass = md[i1] * md[i2];
+        } else if (c == 1) {
+            pbase = i0 + ND * ND * i2, pst = ND, ic = i1, mass = md[i0] * md[i2];
+        } else {
+            pbase = i0 + ND * i1, pst = ND * ND, ic = i2, mass = md[i0] * md[i1];
+        }
         T acc = 0;
-        for (int q = 0; q < ND; ++q) acc += Dp[q * NC + ic] * p[pbase + q * ps[c]];
+        for (int q = 0; q < ND; ++q) acc += Dp[q * NC + ic] * p[pbase + q * pst];
         vel[idx] = -mass * acc;
     }
 }
 
 // p = B vel (all three components summed), returns nothing; caller projects
-template <int K, typename T>
+template <int K, int NTP, typename T>
 __device__ inline void apply_B(const T* vel, T* p, const T* Dp, const T* md) {
-    using P = PatchShape<K>;
+    using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV, NC = P::NC, ND = P::ND;
     for (int idx = threadIdx.x; idx < P::NP; idx += P::NT) {
         const int q[3] = {idx % ND, (idx / ND) % ND, idx / (ND * ND)};
@@ -154,8 +284,11 @@ struct PatchIndex {
     size_t nc;
     template <int K>
     __device__ size_t vel(int c, int e) const {
-        const int e0 = ext<K>(c, 0), e1 = ext<K>(c, 1);
-        const int i0 = bx + e % e0, i1 = by + (e / e0) % e1, i2 = bz + e / (e0 * e1);
+        int i0, i1, i2;
+        vel_coords<K>(c, e, i0, i1, i2);
+        i0 += bx;
+        i1 += by;
+        i2 += bz;
         if (c == 0) return size_t(i0) + size_t(N1 - 1) * (i1 + size_t(N1) * i2);
         if (c == 1) return nc + i0 + size_t(N1) * (i1 + size_t(N1 - 1) * i2);
         return 2 * nc + i0 + size_t(N1) * (i1 + size_t(N1) * i2);
@@ -168,17 +301,17 @@ struct PatchIndex {
     }
 };
 
-template <int K, typename T>
-__global__ void __launch_bounds__(256)
+template <int K, typename T, int NTP = 0>
+__global__ void __launch_bounds__((PatchShape<K, NTP>::NT))
 patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restrict__ tab, int n, int colour,
                    int cntx, int cnty, T cg_rtol, int cg_maxit, int* __restrict__ counters, int boundary_only) {
-    using P = PatchShape<K>;
+    using P = PatchShape<K, NTP>;
     using PT = PatchTab<K>;
-    constexpr int NV = P::NV, NP = P::NP, NC = P::NC, ND = P::ND;
+    constexpr int NV = P::NV, NP = P::NP, ND = P::ND, NW = P::NW;
     __shared__ T s_tab[PT::size];
-    __shared__ T F[3 * NV], V1[3 * NV], W1[3 * NV], W2[3 * NV];
+    __shared__ T V1[3 * NV], W1[3 * NV];
     __shared__ T Pv[NP], R[NP], Dv[NP], Q[NP];
-    __shared__ T red[4];
+    __shared__ T red[2 * NW];
 
     const int tid = threadIdx.x;
     // vertex of this workgroup: coordinates of parity (colour bit) in 1..n-1
@@ -195,10 +328,10 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     PatchIndex gi{N1, (vx - 1) * P::M, (vy - 1) * P::M, (vz - 1) * P::M, size_t(N1 - 1) * N1 * N1};
 
     for (int i = tid; i < PT::size; i += P::NT) s_tab[i] = tab[i];
-    // gather R_j r
+    // gather R_j r: F into V1 (A^{-1} F is formed in place), G into R
     for (int i = tid; i < 3 * NV; i += P::NT) {
         const int c = i / NV;
-        F[i] = r[gi.template vel<K>(c, i - c * NV)];
+        V1[i] = r[gi.template vel<K>(c, i - c * NV)];
     }
     for (int i = tid; i < NP; i += P::NT) R[i] = r[gi.template pres<K>(i)];
     __syncthreads();
@@ -221,14 +354,12 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     {
         T s = 0;
         for (int i = tid; i < NP; i += P::NT) s += R[i];
-        const T mean = block_sum(s, red) / T(NP);
+        const T mean = block_sum<NW>(s, red) / T(NP);
         for (int i = tid; i < NP; i += P::NT) R[i] -= mean;
     }
     // V1 = A^{-1} F;  rhs = B V1 - G (projected)
-    for (int i = tid; i < 3 * NV; i += P::NT) V1[i] = F[i];
-    __syncthreads();
-    fd_inverse<K, T>(V1, W1, W2, Sdir, Ldir);
-    apply_B<K, T>(V1, Q, Dp, md);
+    fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir);
+    apply_B<K, NTP, T>(V1, Q, Dp, md);
     __syncthreads();
     T rr;
     {
@@ -237,7 +368,7 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
             Q[i] -= R[i];
             s += Q[i];
         }
-        const T mean = block_sum(s, red) / T(NP);
+        const T mean = block_sum<NW>(s, red) / T(NP);
         T s2 = 0;
         for (int i = tid; i < NP; i += P::NT) {
             const T v = Q[i] - mean;
@@ -246,24 +377,23 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
             Pv[i] = 0;
             s2 += v * v;
         }
-        rr = block_sum(s2, red);
+        rr = block_sum<NW>(s2, red);
     }
     const T rr0 = rr;
     int it = 0;
     while (it < cg_maxit && rr > cg_rtol * cg_rtol * rr0 && rr > T(0)) {
         // Q = S Dv = B A^{-1} B^T Dv, projected to mean zero
-        apply_BT<K, T>(Dv, V1, Dp, md);
+        apply_BT<K, NTP, T>(Dv, V1, Dp, md);
         __syncthreads();
-        fd_inverse<K, T>(V1, W1, W2, Sdir, Ldir);
-        apply_B<K, T>(V1, Q, Dp, md);
+        fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir);
+        apply_B<K, NTP, T>(V1, Q, Dp, md);
         __syncthreads();
         T s = 0, dq = 0;
         for (int i = tid; i < NP; i += P::NT) {
             s += Q[i];
             dq += Dv[i] * Q[i];
         }
-        s = block_sum(s, red);
-        dq = block_sum(dq, red);   // Dv has zero mean, so Dv . (Q - mean) = Dv . Q
+        block_sum2<NW>(s, dq, red);   // Dv has zero mean, so Dv . (Q - mean) = Dv . Q
         const T mean = s / T(NP);
         const T alpha = rr / dq;
         T s2 = 0;
@@ -273,26 +403,29 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
             R[i] = ri;
             s2 += ri * ri;
         }
-        const T rr_new = block_sum(s2, red);
+        const T rr_new = block_sum<NW>(s2, red);
         const T beta = rr_new / rr;
         for (int i = tid; i < NP; i += P::NT) Dv[i] = R[i] + beta * Dv[i];
         rr = rr_new;
         ++it;
         __syncthreads();
     }
-    // U = A^{-1} (F - B^T P)
+    // U = A^{-1} (F - B^T P), F gathered again (r is not written during the colour)
     {
         T s = 0;
         for (int i = tid; i < NP; i += P::NT) s += Pv[i];
-        const T mean = block_sum(s, red) / T(NP);
+        const T mean = block_sum<NW>(s, red) / T(NP);
         for (int i = tid; i < NP; i += P::NT) Pv[i] -= mean;
         __syncthreads();
     }
-    apply_BT<K, T>(Pv, V1, Dp, md);
+    apply_BT<K, NTP, T>(Pv, V1, Dp, md);
     __syncthreads();
-    for (int i = tid; i < 3 * NV; i += P::NT) V1[i] = F[i] - V1[i];
+    for (int i = tid; i < 3 * NV; i += P::NT) {
+        const int c = i / NV;
+        V1[i] = r[gi.template vel<K>(c, i - c * NV)] - V1[i];
+    }
     __syncthreads();
-    fd_inverse<K, T>(V1, W1, W2, Sdir, Ldir);
+    fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir);
     // scatter x += R_j^T (U, P); the DoF sets of one colour are disjoint
     for (int i = tid; i < 3 * NV; i += P::NT) {
         const int c = i / NV;
