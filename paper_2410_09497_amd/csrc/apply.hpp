@@ -15,7 +15,9 @@ template <int K>
 hipError_t launch_apply_k(bool f64, bool resid, const void* x, const void* b, void* y, const void* tab, int n,
                           hipStream_t st);
 
-// workgroups per z column of tiles: >= 2048 workgroups, chunks >= 4 layers
-int apply_chunk_layers(int n, int blocks_xy);
+// cell layers per workgroup along z (per degree; STOKESMG_APPLY_CZ overrides), for the
+// tile kernels and for the wave-per-position kernel
+int apply_chunk_layers(int k, int n, int blocks_xy);
+int apply_chunk_layers_position(int n, int blocks_xy);
 
 }  // namespace smg

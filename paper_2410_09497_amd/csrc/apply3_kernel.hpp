@@ -1,0 +1,316 @@
+// Fused operator y = K x (or r = b - K x), 2.5D tile kernel with the work of
+// every xy position split between two wave groups (Alg. 1 in the separable
+// form of stencil_tables.hpp; same arithmetic as apply_kernel.hpp).
+//
+// Group A (the first NA threads, whole waves) owns y_x and y_y of its
+// position: the in-plane rows Lc, D^T and Ld on Mc u, and the z stencil Ld_z
+// on Mc_x u_x and Mc_y u_y from its register windows.  Group B owns y_z and
+// y_p: the in-plane Ld rows on u_z, the divergence rows D u, and the z
+// stencils Mc_z, Lc_z, D^T_z, D_z from its windows; it also forms the shared
+// Mc_x u_x / Mc_y u_y planes while group A evaluates its first in-plane
+// terms.  Each group runs its own copy of the layer loop, so a thread keeps
+// only its group's windows live (about half the registers of one thread per
+// position), and a CU holds twice as many waves.  Both copies pass the same
+// barriers in the same order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "apply_kernel.hpp"
+#include "stencil_tables.hpp"
+
+namespace smg {
+
+template <int K, int CX, int CY>
+struct SplitShape {
+    static constexpr int M = K + 1;
+    static constexpr int TX = CX * M, TY = CY * M;
+    static constexpr int NP = TX * TY;                  // positions
+    static constexpr int NA = (NP + 63) / 64 * 64;      // threads per group (whole waves)
+    static constexpr int NT = 2 * NA;
+    static constexpr int RX = TX + 2 * M, RY = TY + 2 * M;
+    static constexpr int RS = RX * RY;
+    static constexpr int NL = (RS + NT - 1) / NT;       // plane elements per thread and field
+};
+
+template <int K, typename T, int CX, int CY, bool RESID, int ROLE>
+__device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__ bvec, T* __restrict__ y,
+                                  const T* __restrict__ s_tab, T (*s_u)[4][SplitShape<K, CX, CY>::RS], T* s_vx,
+                                  T* s_vy, int n, int L0, int L1, int X0, int Y0) {
+    using S = SplitShape<K, CX, CY>;
+    constexpr int M = S::M, TX = S::TX, TY = S::TY, NP = S::NP, NA = S::NA, NT = S::NT, RX = S::RX, RY = S::RY,
+                  RS = S::RS, NL = S::NL;
+    using TB = Tab<K>;
+    const int tid = threadIdx.x;
+    const int p = tid - ROLE * NA;                 // position of this thread in its group
+    const bool act = p < NP;
+    const int tx = act ? p % TX : 0, ty = act ? p / TX : 0;
+    const int X = X0 + tx, Y = Y0 + ty;
+    const int a = tx % M, b = ty % M;
+    const int N1 = n * M;
+    const int vxv = ld_variant(X / M, n), vyv = ld_variant(Y / M, n);
+    const size_t nc = size_t(N1 - 1) * N1 * N1;
+    const T* __restrict__ gx = x;
+    const T* __restrict__ gy = x + nc;
+    const T* __restrict__ gz = x + 2 * nc;
+    const T* __restrict__ gp = x + 3 * nc;
+    const T mda = s_tab[TB::MDg + a], mdb = s_tab[TB::MDg + b];
+    // The stencil rows are re-read from LDS where they are used: the table
+    // base goes through an SGPR move the compiler cannot see through, so the
+    // per-thread rows are not hoisted out of the layer loop into registers.
+    auto tables = [&]() {
+        int z;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+        return s_tab + z;
+    };
+
+    // plane Z of the four fields, tile + halo, zero outside the domain (all threads share the loads)
+    auto load_plane = [&](int Z, T (&v)[4][NL]) {
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int i = tid + t * NT;
+            const int gxp = X0 - M + i % RX, gyp = Y0 - M + i / RX;
+            const bool in = i < RS && gxp >= 0 && gxp < N1 && gyp >= 0 && gyp < N1;
+            T vux = 0, vuy = 0, vuz = 0, vp = 0;
+            if (in) {
+                if (gxp < N1 - 1) vux = gx[gxp + size_t(N1 - 1) * (gyp + size_t(N1) * Z)];
+                if (gyp < N1 - 1) vuy = gy[gxp + size_t(N1) * (gyp + size_t(N1 - 1) * Z)];
+                if (Z < N1 - 1) vuz = gz[gxp + size_t(N1) * (gyp + size_t(N1) * Z)];
+                vp = gp[gxp + size_t(N1) * (gyp + size_t(N1) * Z)];
+            }
+            v[0][t] = vux;
+            v[1][t] = vuy;
+            v[2][t] = vuz;
+            v[3][t] = vp;
+        }
+    };
+
+    // group A: windows of Mc_x u_x, Mc_y u_y and the in-plane partials of y_x, y_y;
+    // group B: windows of the in-plane Ld u_z, of u_z and of p, and the partial of y_p
+    constexpr int W = 3 * M;
+    T w0[W], w1[W], w2[ROLE == 1 ? W : 1];
+    T q0[2][M], q1[ROLE == 0 ? 2 : 1][M];
+#pragma unroll
+    for (int i = 0; i < W; ++i) w0[i] = w1[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < (ROLE == 1 ? W : 1); ++i) w2[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        q0[0][i] = q0[1][i] = T(0);
+        q1[0][i] = T(0);
+        q1[ROLE == 0 ? 1 : 0][i] = T(0);
+    }
+
+    T pf[4][NL];
+    const int Zlast = (L1 < n ? L1 + 1 : n) * M - 1;
+    load_plane((L0 > 0 ? L0 - 1 : 0) * M, pf);
+
+    int buf = 0;
+    for (int Lin = L0 - 1; Lin <= L1; ++Lin) {
+        const bool have = (Lin >= 0) && (Lin < n);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            T r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0;
+            if (have) {
+                const int Z = Lin * M + c;
+                T* su = &s_u[buf][0][0];
+                // 1) the prefetched plane into LDS, the next plane's loads in flight
+#pragma unroll
+                for (int t = 0; t < NL; ++t) {
+                    const int i = tid + t * NT;
+                    if (i < RS) {
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) su[f * RS + i] = pf[f][t];
+                    }
+                }
+                if (Z < Zlast) load_plane(Z + 1, pf);
+                __syncthreads();
+                const T* sux = su;
+                const T* suy = su + RS;
+                const T* suz = su + 2 * RS;
+                const T* sp = su + 3 * RS;
+                const int rx = tx + M, ry = ty + M;
+                const T* tb = tables();
+                const T* __restrict__ MC = tb + TB::MC;
+                const T* __restrict__ LC = tb + TB::LC;
+                const T* __restrict__ DT = tb + TB::DT;
+                const T* __restrict__ DD = tb + TB::DD;
+                const T* __restrict__ LD = tb + TB::LD;
+                const T mdc = tb[TB::MDg + c];
+                T lcx = 0, dtx = 0, lcy = 0, dty = 0;
+                if constexpr (ROLE == 1) {
+                    // 2B) Mc along x for the rows the y stencil needs, Mc along y for the columns
+                    for (int i = p; i < TX * RY; i += NA) {
+                        const int qx = i % TX, qy = i / TX;
+                        const T* row = MC + (qx % M) * (2 * M + 1);
+                        const T* src = sux + qy * RX + qx;
+                        T acc = 0;
+#pragma unroll
+                        for (int o = 0; o < 2 * M + 1; ++o) acc += row[o] * src[o];
+                        s_vx[i] = acc;
+                    }
+                    for (int i = p; i < RX * TY; i += NA) {
+                        const int qx = i % RX, qy = i / RX;
+                        const T* row = MC + (qy % M) * (2 * M + 1);
+                        const T* src = suy + qy * RX + qx;
+                        T acc = 0;
+#pragma unroll
+                        for (int o = 0; o < 2 * M + 1; ++o) acc += row[o] * src[o * RX];
+                        s_vy[i] = acc;
+                    }
+                } else if (act) {
+                    // 2A) the in-plane rows that need only the raw plane
+                    const T* rux = sux + ry * RX;
+#pragma unroll
+                    for (int o = 0; o < 2 * M + 1; ++o) {
+                        lcx += LC[a * (2 * M + 1) + o] * rux[rx + o - M];
+                        lcy += LC[b * (2 * M + 1) + o] * suy[(ry + o - M) * RX + rx];
+                    }
+#pragma unroll
+                    for (int o = 0; o < 2 * M; ++o) {
+                        dtx += DT[a * 2 * M + o] * sp[ry * RX + tx - a + M + o];
+                        dty += DT[b * 2 * M + o] * sp[(ty - b + M + o) * RX + rx];
+                    }
+                }
+                __syncthreads();
+                // 3) the remaining in-plane terms at this thread's position
+                if (act) {
+                    if constexpr (ROLE == 0) {
+                        T ldyvx = 0, ldxvy = 0;
+#pragma unroll
+                        for (int o = 0; o < 3 * M; ++o) {
+                            ldyvx += LD[vyv * 3 * M * M + b * 3 * M + o] * s_vx[(ty - b + o) * TX + tx];
+                            ldxvy += LD[vxv * 3 * M * M + a * 3 * M + o] * s_vy[ty * RX + tx - a + o];
+                        }
+                        r0 = mdb * mdc * (lcx - dtx) + mdc * ldyvx;   // in-plane part of y_x
+                        r1 = mda * mdc * (lcy - dty) + mdc * ldxvy;   // in-plane part of y_y
+                        r2 = s_vx[ry * TX + tx];                      // Mc_x u_x at this position
+                        r3 = s_vy[ty * RX + rx];                      // Mc_y u_y
+                    } else {
+                        T ldxuz = 0, ldyuz = 0, dxux = 0, dyuy = 0;
+#pragma unroll
+                        for (int o = 0; o < 3 * M; ++o) {
+                            ldxuz += LD[vxv * 3 * M * M + a * 3 * M + o] * suz[ry * RX + tx - a + o];
+                            ldyuz += LD[vyv * 3 * M * M + b * 3 * M + o] * suz[(ty - b + o) * RX + rx];
+                        }
+                        const T* rux = sux + ry * RX;
+#pragma unroll
+                        for (int j = 0; j < M + 1; ++j) {
+                            dxux += DD[a * (M + 1) + j] * rux[tx - a + M + j - 1];
+                            dyuy += DD[b * (M + 1) + j] * suy[(ty - b + M + j - 1) * RX + rx];
+                        }
+                        r0 = mdb * ldxuz + mda * ldyuz;                // in-plane Ld on u_z
+                        r1 = suz[ry * RX + rx];                        // u_z
+                        r2 = sp[ry * RX + rx];                         // p
+                        r3 = -mdc * (mdb * dxux + mda * dyuy);         // in-plane part of y_p
+                    }
+                }
+                buf ^= 1;
+            }
+            if constexpr (ROLE == 0) {
+                w0[2 * M + c] = r2;
+                w1[2 * M + c] = r3;
+                q0[1][c] = r0;
+                q1[1][c] = r1;
+            } else {
+                w0[2 * M + c] = r0;
+                w1[2 * M + c] = r1;
+                w2[2 * M + c] = r2;
+                q0[1][c] = r3;
+            }
+            (void)r4;
+        }
+
+        // 4) layer Lin-1 is complete: z stencils from the windows, write it
+        const int L = Lin - 1;
+        if (L >= L0) {
+            const bool okxy = act && X < N1 && Y < N1;
+            const T* tb = tables();
+            const T* __restrict__ MC = tb + TB::MC;
+            const T* __restrict__ LC = tb + TB::LC;
+            const T* __restrict__ DT = tb + TB::DT;
+            const T* __restrict__ DD = tb + TB::DD;
+            const T* __restrict__ LD = tb + TB::LD;
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const int Z = L * M + c;
+                const size_t oz = X + size_t(N1) * (Y + size_t(N1) * Z);
+                if constexpr (ROLE == 0) {
+                    const T* LDz = LD + ld_variant(L, n) * 3 * M * M;
+                    T zx = 0, zy = 0;
+#pragma unroll
+                    for (int o = 0; o < 3 * M; ++o) {
+                        zx += LDz[c * 3 * M + o] * w0[o];
+                        zy += LDz[c * 3 * M + o] * w1[o];
+                    }
+                    const T yx = q0[0][c] + mdb * zx;
+                    const T yy = q1[0][c] + mda * zy;
+                    if (okxy) {
+                        const size_t ox = X + size_t(N1 - 1) * (Y + size_t(N1) * Z);
+                        const size_t oy = X + size_t(N1) * (Y + size_t(N1 - 1) * Z);
+                        if (X < N1 - 1) y[ox] = RESID ? bvec[ox] - yx : yx;
+                        if (Y < N1 - 1) y[nc + oy] = RESID ? bvec[nc + oy] - yy : yy;
+                    }
+                } else {
+                    T zp = 0, zms = 0, zlc = 0, zdt = 0;
+#pragma unroll
+                    for (int j = 0; j < M + 1; ++j) zp += DD[c * (M + 1) + j] * w1[M + j - 1];
+#pragma unroll
+                    for (int o = 0; o < 2 * M + 1; ++o) {
+                        zms += MC[c * (2 * M + 1) + o] * w0[c + o];
+                        zlc += LC[c * (2 * M + 1) + o] * w1[c + o];
+                    }
+#pragma unroll
+                    for (int o = 0; o < 2 * M; ++o) zdt += DT[c * 2 * M + o] * w2[M + o];
+                    const T yp = q0[0][c] - mda * mdb * zp;
+                    const T yz = zms + mda * mdb * (zlc - zdt);
+                    if (okxy) {
+                        if (Z < N1 - 1) y[2 * nc + oz] = RESID ? bvec[2 * nc + oz] - yz : yz;
+                        y[3 * nc + oz] = RESID ? bvec[3 * nc + oz] - yp : yp;
+                    }
+                }
+            }
+        }
+        // 5) slide the windows by one layer
+#pragma unroll
+        for (int i = 0; i < 2 * M; ++i) {
+            w0[i] = w0[i + M];
+            w1[i] = w1[i + M];
+            if constexpr (ROLE == 1) w2[i] = w2[i + M];
+        }
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            q0[0][i] = q0[1][i];
+            if constexpr (ROLE == 0) q1[0][i] = q1[1][i];
+        }
+    }
+}
+
+template <int K, typename T, int CX, int CY, bool RESID>
+__global__ void __launch_bounds__((SplitShape<K, CX, CY>::NT))
+stokes_apply_split_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T* __restrict__ y,
+                          const T* __restrict__ tab, int n, int cz, int tiles_x, int tiles_y) {
+    using S = SplitShape<K, CX, CY>;
+    using TB = Tab<K>;
+    __shared__ T s_tab[TB::size];
+    __shared__ T s_u[2][4][S::RS];        // ux, uy, uz, p planes (double buffered)
+    __shared__ T s_vx[S::TX * S::RY];     // Mc_x ux over tile columns x all region rows
+    __shared__ T s_vy[S::RX * S::TY];     // Mc_y uy over all region columns x tile rows
+    for (int i = threadIdx.x; i < TB::size; i += S::NT) s_tab[i] = tab[i];
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile_x = lin % tiles_x;
+    const int rest = lin / tiles_x;
+    const int tile_y = rest % tiles_y;
+    const int zc = rest / tiles_y;
+    const int L0 = zc * cz;
+    const int L1 = (L0 + cz < n) ? L0 + cz : n;
+    const int X0 = tile_x * S::TX, Y0 = tile_y * S::TY;
+    __syncthreads();
+    // the groups are whole waves; each runs its copy of the layer loop (same barriers, same order)
+    if (threadIdx.x < S::NA)
+        split_loop<K, T, CX, CY, RESID, 0>(x, bvec, y, s_tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
+    else
+        split_loop<K, T, CX, CY, RESID, 1>(x, bvec, y, s_tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
+}
+
+}  // namespace smg

@@ -8,6 +8,7 @@
 
 #include "apply.hpp"
 #include "apply2_kernel.hpp"
+#include "apply3_kernel.hpp"
 #include "apply_kernel.hpp"
 
 namespace smg {
@@ -26,10 +27,24 @@ hipError_t launch_generic(const void* x, const void* b, void* y, const void* tab
     const int N1 = n * S::M;
     const int tiles_x = (N1 + S::TX - 1) / S::TX;
     const int tiles_y = (N1 + S::TY - 1) / S::TY;
-    const int cz = apply_chunk_layers(n, tiles_x * tiles_y);
+    const int cz = apply_chunk_layers(K, n, tiles_x * tiles_y);
     const int nzc = (n + cz - 1) / cz;
     hipLaunchKernelGGL((stokes_apply_kernel<K, T, CX, CY, RESID, PF>), dim3(tiles_x * tiles_y * nzc), dim3(S::NT), 0,
                        st, static_cast<const T*>(x), static_cast<const T*>(b), static_cast<T*>(y),
+                       static_cast<const T*>(tab), n, cz, tiles_x, tiles_y);
+    return hipGetLastError();
+}
+
+template <int K, typename T, bool RESID, int CX = TileOf<K>::CX, int CY = TileOf<K>::CY>
+hipError_t launch_split(const void* x, const void* b, void* y, const void* tab, int n, hipStream_t st) {
+    using S = SplitShape<K, CX, CY>;
+    const int N1 = n * S::M;
+    const int tiles_x = (N1 + S::TX - 1) / S::TX;
+    const int tiles_y = (N1 + S::TY - 1) / S::TY;
+    const int cz = apply_chunk_layers(K, n, tiles_x * tiles_y);
+    const int nzc = (n + cz - 1) / cz;
+    hipLaunchKernelGGL((stokes_apply_split_kernel<K, T, CX, CY, RESID>), dim3(tiles_x * tiles_y * nzc), dim3(S::NT),
+                       0, st, static_cast<const T*>(x), static_cast<const T*>(b), static_cast<T*>(y),
                        static_cast<const T*>(tab), n, cz, tiles_x, tiles_y);
     return hipGetLastError();
 }
@@ -38,7 +53,7 @@ template <int K, typename T, bool RESID>
 hipError_t launch_wave_position(const void* x, const void* b, void* y, int n, hipStream_t st) {
     using S = Ap2<K>;
     const int tiles = (n + S::C - 1) / S::C;
-    const int cz = apply_chunk_layers(n, tiles * tiles);
+    const int cz = apply_chunk_layers_position(n, tiles * tiles);
     const int nzc = (n + cz - 1) / cz;
     hipLaunchKernelGGL((apply2_kernel<K, T, RESID>), dim3(tiles * tiles * nzc), dim3(S::NT), 0, st,
                        static_cast<const T*>(x), static_cast<const T*>(b), static_cast<T*>(y), n, cz, tiles,
@@ -47,13 +62,10 @@ hipError_t launch_wave_position(const void* x, const void* b, void* y, int n, hi
 }
 
 // Kernel choice.  Defaults are the fastest measured on MI355X at 64^3 cells
-// (HBM-resident); STOKESMG_APPLY_KERNEL = generic | pipelined | position and
-// STOKESMG_APPLY_TILE = CXxCY (degree 2: 8x4, 8x3, 6x4, 5x5; degree 5: 4x2, 2x2)
-// override them
-// for comparison runs.
+// (HBM-resident); STOKESMG_APPLY_KERNEL = generic | pipelined | position | split
+// overrides them for comparison runs.
 struct ApplyChoice {
-    int kernel = 0;   // 0 default, 1 generic, 2 generic with pipelined loads, 3 wave per position
-    int cx = 0, cy = 0;
+    int kernel = 0;   // 0 default, 1 generic, 2 generic with pipelined loads, 3 wave per position, 4 split groups
 };
 inline ApplyChoice apply_choice() {
     static const ApplyChoice c = [] {
@@ -62,10 +74,7 @@ inline ApplyChoice apply_choice() {
             if (!std::strcmp(s, "generic")) r.kernel = 1;
             else if (!std::strcmp(s, "pipelined")) r.kernel = 2;
             else if (!std::strcmp(s, "position")) r.kernel = 3;
-        }
-        if (const char* s = std::getenv("STOKESMG_APPLY_TILE")) {
-            int a = 0, b = 0;
-            if (std::sscanf(s, "%dx%d", &a, &b) == 2) r.cx = a, r.cy = b;
+            else if (!std::strcmp(s, "split")) r.kernel = 4;
         }
         return r;
     }();
@@ -74,33 +83,21 @@ inline ApplyChoice apply_choice() {
 
 // measured defaults per degree and precision
 template <int K> constexpr bool position_default(bool f64) { return K == 1 && !f64; }
+template <int K> constexpr bool split_default(bool f64) { return K == 3 || K == 5 || (K == 2 && f64) || (K == 4 && !f64); }
 template <int K> constexpr bool pipelined_default(bool f64) { return K <= 4 || !f64; }
-
-template <int K, typename T, bool R, bool PF>
-hipError_t launch_generic_tile(int cx, int cy, const void* x, const void* b, void* y, const void* tab, int n,
-                               hipStream_t st) {
-    if constexpr (K == 2) {
-        if (cx == 8 && cy == 4) return launch_generic<K, T, R, 8, 4, PF>(x, b, y, tab, n, st);
-        if (cx == 8 && cy == 3) return launch_generic<K, T, R, 8, 3, PF>(x, b, y, tab, n, st);
-        if (cx == 6 && cy == 4) return launch_generic<K, T, R, 6, 4, PF>(x, b, y, tab, n, st);
-        if (cx == 5 && cy == 5) return launch_generic<K, T, R, 5, 5, PF>(x, b, y, tab, n, st);
-    }
-    if constexpr (K == 5) {
-        if (cx == 4 && cy == 2) return launch_generic<K, T, R, 4, 2, PF>(x, b, y, tab, n, st);
-        if (cx == 2 && cy == 2) return launch_generic<K, T, R, 2, 2, PF>(x, b, y, tab, n, st);
-    }
-    return launch_generic<K, T, R, TileOf<K>::CX, TileOf<K>::CY, PF>(x, b, y, tab, n, st);
-}
 
 template <int K, typename T, bool R>
 hipError_t launch_degree_t(bool f64, const void* x, const void* b, void* y, const void* tab, int n, hipStream_t st) {
     const ApplyChoice c = apply_choice();
     // the wave-per-position kernel is wrong in FP64 at degree 3: never used there
     const bool position = (c.kernel == 3 || (c.kernel == 0 && position_default<K>(f64))) && !(K == 3 && f64);
-    if (position) return launch_wave_position<K, T, R>(x, b, y, n, st);
+    // the wave-per-position kernel is built for degrees 1..3 only
+    if constexpr (K <= 3)
+        if (position) return launch_wave_position<K, T, R>(x, b, y, n, st);
+    if (c.kernel == 4 || (c.kernel == 0 && split_default<K>(f64))) return launch_split<K, T, R>(x, b, y, tab, n, st);
     const bool pf = c.kernel == 2 || (c.kernel == 0 && pipelined_default<K>(f64));
-    return pf ? launch_generic_tile<K, T, R, true>(c.cx, c.cy, x, b, y, tab, n, st)
-              : launch_generic_tile<K, T, R, false>(c.cx, c.cy, x, b, y, tab, n, st);
+    return pf ? launch_generic<K, T, R, TileOf<K>::CX, TileOf<K>::CY, true>(x, b, y, tab, n, st)
+              : launch_generic<K, T, R, TileOf<K>::CX, TileOf<K>::CY, false>(x, b, y, tab, n, st);
 }
 
 template <int K>
