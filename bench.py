@@ -36,7 +36,8 @@ if ROOT not in sys.path:
 
 METRIC = "Stokes apply DoF/s (%HBM roofline); time to 1e-8 res, FP64 MG vs FP32/learned MG"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2410_09497_amd/csrc/apply_kernel.hpp", "paper_2410_09497_amd/csrc/apply_launch.hpp",
+KERNEL_SOURCES = ["paper_2410_09497_amd/csrc/apply_kernel.hpp", "paper_2410_09497_amd/csrc/apply3_kernel.hpp",
+                  "paper_2410_09497_amd/csrc/apply_launch.hpp",
                   "paper_2410_09497_amd/csrc/apply_common.cpp", "paper_2410_09497_amd/csrc/stencil_tables.hpp",
                   "paper_2410_09497_amd/csrc/apply_k{k}.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic.json")
@@ -263,7 +264,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "stokes_apply_kernel",
+                     "kernel": "stokes_apply (the fused operator kernel dispatched for this degree and dtype)",
                      "algorithmic_bytes_per_launch": alg_bytes},
         "copy_GBps_same_bytes": copy_gbs,
         "context": "paper (A100, FP64): > 1 GDoF/s operator evaluation; 0.535 ns/DoF = 1.87 GDoF/s "

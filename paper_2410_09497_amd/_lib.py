@@ -4,6 +4,13 @@ built this module raises at import."""
 import ctypes
 import os
 
+try:
+    # torch ships its own HIP runtime; it must be the process's only one, so it is
+    # loaded before libstokesmg (whose libamdhip64 dependency then resolves to it)
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstokesmg.so")
 
