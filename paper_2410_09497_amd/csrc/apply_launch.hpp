@@ -83,7 +83,8 @@ inline ApplyChoice apply_choice() {
 
 // measured defaults per degree and precision
 template <int K> constexpr bool position_default(bool f64) { return K == 1 && !f64; }
-template <int K> constexpr bool split_default(bool f64) { return K == 3 || K == 5 || (K == 2 && f64) || (K == 4 && !f64); }
+// (degree 2 also compared 8x4, 6x4, 7x3 and 5x5 tiles and 16-layer chunks for the split kernel: all slower)
+template <int K> constexpr bool split_default(bool f64) { return K == 2 || K == 3 || K == 5 || (K == 4 && !f64); }
 template <int K> constexpr bool pipelined_default(bool f64) { return K <= 4 || !f64; }
 
 template <int K, typename T, bool R>
