@@ -63,6 +63,21 @@ __device__ constexpr int ext(int c, int d) {
     return d == c ? 2 * K + 1 : 2 * K + 2;
 }
 
+// Packed coordinates of velocity entry idx (component c, position (i0, i1, i2)
+// in its box): c | i0 << 2 | i1 << 8 | i2 << 14.  A table of them sits in LDS,
+// filled once per workgroup, so the passes read one word instead of redoing
+// the division chain of every entry.
+__device__ inline int code_c(int v) { return v & 3; }
+__device__ inline int code_i(int v, int d) { return (v >> (2 + 6 * d)) & 63; }
+template <int K>
+__device__ inline int vel_code(int idx) {
+    constexpr int NV = (2 * K + 1) * (2 * K + 2) * (2 * K + 2);
+    const int c = idx / NV;
+    int i0, i1, i2;
+    vel_coords<K>(c, idx - c * NV, i0, i1, i2);
+    return c | (i0 << 2) | (i1 << 8) | (i2 << 14);
+}
+
 // block-wide sums of one or two values per thread (NW waves; red holds 2 NW)
 template <int NW, typename T>
 __device__ inline T block_sum(T v, T* red) {
@@ -105,21 +120,25 @@ __device__ inline void block_sum2(T& a, T& b, T* red) {
 // out[comp] = contraction of in[comp] along direction d with matrix
 // S_(comp, d) (transposed if TR), for the three velocity components at once.
 template <int K, int NTP, typename T, bool TR>
-__device__ inline void contract3(const T* in, T* out, int d, const T* const* Sdir) {
+__device__ inline void contract3(const T* in, T* out, int d, const T* const* Sdir, const int* codes) {
     using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV, NC = P::NC, ND = P::ND;
     for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
-        const int c = idx / NV, e = idx - c * NV;
-        int i[3];
-        vel_coords<K>(c, e, i[0], i[1], i[2]);
+        const int code = codes[idx];
+        const int c = code_c(code);
+        const int ii = code_i(code, d);
         const int e0 = c == 0 ? NC : ND, e1 = c == 1 ? NC : ND;
-        const int ii = i[d];
-        const int nd = d == c ? NC : ND;
         const int st = d == 0 ? 1 : (d == 1 ? e0 : e0 * e1);
-        const T* base = in + c * NV + e - ii * st;
+        const T* base = in + idx - ii * st;
         const T* S = Sdir[c * 3 + d];
         T acc = 0;
-        for (int j = 0; j < nd; ++j) acc += (TR ? S[j * nd + ii] : S[ii * nd + j]) * base[j * st];
+        if (d == c) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) acc += (TR ? S[j * NC + ii] : S[ii * NC + j]) * base[j * st];
+        } else {
+#pragma unroll
+            for (int j = 0; j < ND; ++j) acc += (TR ? S[j * ND + ii] : S[ii * ND + j]) * base[j * st];
+        }
         out[idx] = acc;
     }
 }
@@ -182,18 +201,18 @@ __device__ inline void contract_lines(const T* in, T* out, const T* const* Sdir)
 
 // v <- A^{-1} v for the three components (in place), work buffer w
 template <int K, int NTP, typename T>
-__device__ inline void fd_inverse(T* v, T* w, const T* const* Sdir, const T* const* Ldir) {
+__device__ inline void fd_inverse(T* v, T* w, const T* const* Sdir, const T* const* Ldir, const int* codes) {
     using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV;
     // FP32: a thread per line (fewer LDS reads); FP64: a thread per entry, whose
     // lanes read with unit stride (the lines' strided FP64 reads conflict in the
     // LDS banks and measured slower)
     if constexpr (sizeof(T) == 8) {
-        contract3<K, NTP, T, true>(v, w, 0, Sdir);
+        contract3<K, NTP, T, true>(v, w, 0, Sdir, codes);
         __syncthreads();
-        contract3<K, NTP, T, true>(w, v, 1, Sdir);
+        contract3<K, NTP, T, true>(w, v, 1, Sdir, codes);
         __syncthreads();
-        contract3<K, NTP, T, true>(v, w, 2, Sdir);
+        contract3<K, NTP, T, true>(v, w, 2, Sdir, codes);
     } else {
         contract_lines<K, NTP, T, true, 0>(v, w, Sdir);
         __syncthreads();
@@ -203,18 +222,16 @@ __device__ inline void fd_inverse(T* v, T* w, const T* const* Sdir, const T* con
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
-        const int c = idx / NV, e = idx - c * NV;
-        int i0, i1, i2;
-        vel_coords<K>(c, e, i0, i1, i2);
-        w[idx] /= Ldir[c * 3 + 0][i0] + Ldir[c * 3 + 1][i1] + Ldir[c * 3 + 2][i2];
+        const int code = codes[idx], c = code_c(code);
+        w[idx] /= Ldir[c * 3 + 0][code_i(code, 0)] + Ldir[c * 3 + 1][code_i(code, 1)] + Ldir[c * 3 + 2][code_i(code, 2)];
     }
     __syncthreads();
     if constexpr (sizeof(T) == 8) {
-        contract3<K, NTP, T, false>(w, v, 2, Sdir);
+        contract3<K, NTP, T, false>(w, v, 2, Sdir, codes);
         __syncthreads();
-        contract3<K, NTP, T, false>(v, w, 1, Sdir);
+        contract3<K, NTP, T, false>(v, w, 1, Sdir, codes);
         __syncthreads();
-        contract3<K, NTP, T, false>(w, v, 0, Sdir);
+        contract3<K, NTP, T, false>(w, v, 0, Sdir, codes);
     } else {
         contract_lines<K, NTP, T, false, 2>(w, v, Sdir);
         __syncthreads();
@@ -227,13 +244,12 @@ __device__ inline void fd_inverse(T* v, T* w, const T* const* Sdir, const T* con
 
 // vel = B^T p:  (B^T p)_c[i] = -D^T along c times the DG masses of the other directions
 template <int K, int NTP, typename T>
-__device__ inline void apply_BT(const T* p, T* vel, const T* Dp, const T* md) {
+__device__ inline void apply_BT(const T* p, T* vel, const T* Dp, const T* md, const int* codes) {
     using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV, NC = P::NC, ND = P::ND;
     for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
-        const int c = idx / NV, e = idx - c * NV;
-        int i0, i1, i2;
-        vel_coords<K>(c, e, i0, i1, i2);
+        const int code = codes[idx], c = code_c(code);
+        const int i0 = code_i(code, 0), i1 = code_i(code, 1), i2 = code_i(code, 2);
         // pressure index equals i in the DG directions; the continuous one is summed
         int pbase, pst, ic;
         T mass;
@@ -312,6 +328,7 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     __shared__ T V1[3 * NV], W1[3 * NV];
     __shared__ T Pv[NP], R[NP], Dv[NP], Q[NP];
     __shared__ T red[2 * NW];
+    __shared__ int codes[3 * NV];
 
     const int tid = threadIdx.x;
     // vertex of this workgroup: coordinates of parity (colour bit) in 1..n-1
@@ -328,6 +345,7 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     PatchIndex gi{N1, (vx - 1) * P::M, (vy - 1) * P::M, (vz - 1) * P::M, size_t(N1 - 1) * N1 * N1};
 
     for (int i = tid; i < PT::size; i += P::NT) s_tab[i] = tab[i];
+    for (int i = tid; i < 3 * NV; i += P::NT) codes[i] = vel_code<K>(i);
     // gather R_j r: F into V1 (A^{-1} F is formed in place), G into R
     for (int i = tid; i < 3 * NV; i += P::NT) {
         const int c = i / NV;
@@ -358,7 +376,7 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
         for (int i = tid; i < NP; i += P::NT) R[i] -= mean;
     }
     // V1 = A^{-1} F;  rhs = B V1 - G (projected)
-    fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir);
+    fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir, codes);
     apply_B<K, NTP, T>(V1, Q, Dp, md);
     __syncthreads();
     T rr;
@@ -383,9 +401,9 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     int it = 0;
     while (it < cg_maxit && rr > cg_rtol * cg_rtol * rr0 && rr > T(0)) {
         // Q = S Dv = B A^{-1} B^T Dv, projected to mean zero
-        apply_BT<K, NTP, T>(Dv, V1, Dp, md);
+        apply_BT<K, NTP, T>(Dv, V1, Dp, md, codes);
         __syncthreads();
-        fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir);
+        fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir, codes);
         apply_B<K, NTP, T>(V1, Q, Dp, md);
         __syncthreads();
         T s = 0, dq = 0;
@@ -418,14 +436,14 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
         for (int i = tid; i < NP; i += P::NT) Pv[i] -= mean;
         __syncthreads();
     }
-    apply_BT<K, NTP, T>(Pv, V1, Dp, md);
+    apply_BT<K, NTP, T>(Pv, V1, Dp, md, codes);
     __syncthreads();
     for (int i = tid; i < 3 * NV; i += P::NT) {
         const int c = i / NV;
         V1[i] = r[gi.template vel<K>(c, i - c * NV)] - V1[i];
     }
     __syncthreads();
-    fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir);
+    fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir, codes);
     // scatter x += R_j^T (U, P); the DoF sets of one colour are disjoint
     for (int i = tid; i < 3 * NV; i += P::NT) {
         const int c = i / NV;
