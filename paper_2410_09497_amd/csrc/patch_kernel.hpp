@@ -119,26 +119,34 @@ __device__ inline void block_sum2(T& a, T& b, T* red) {
 
 // out[comp] = contraction of in[comp] along direction d with matrix
 // S_(comp, d) (transposed if TR), for the three velocity components at once.
-template <int K, int NTP, typename T, bool TR>
-__device__ inline void contract3(const T* in, T* out, int d, const T* const* Sdir, const int* codes) {
+// one entry of contract3 for component C along direction D: every stride is a
+// compile-time constant, so the LDS reads use immediate offsets
+template <int K, typename T, bool TR, int C, int D>
+__device__ inline T contract_entry(const T* in, int idx, int ii, const T* S) {
+    constexpr int NC = 2 * K + 1, ND = 2 * K + 2;
+    constexpr int e0 = C == 0 ? NC : ND, e1 = C == 1 ? NC : ND;
+    constexpr int st = D == 0 ? 1 : (D == 1 ? e0 : e0 * e1);
+    constexpr int n = C == D ? NC : ND;
+    const T* base = in + idx - ii * st;
+    const T* row = TR ? S + ii : S + ii * n;
+    T acc = 0;
+#pragma unroll
+    for (int j = 0; j < n; ++j) acc += row[TR ? j * n : j] * base[j * st];
+    return acc;
+}
+
+template <int K, int NTP, typename T, bool TR, int D>
+__device__ inline void contract3(const T* in, T* out, const T* const* Sdir, const int* codes) {
     using P = PatchShape<K, NTP>;
-    constexpr int NV = P::NV, NC = P::NC, ND = P::ND;
+    constexpr int NV = P::NV;
     for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
         const int code = codes[idx];
         const int c = code_c(code);
-        const int ii = code_i(code, d);
-        const int e0 = c == 0 ? NC : ND, e1 = c == 1 ? NC : ND;
-        const int st = d == 0 ? 1 : (d == 1 ? e0 : e0 * e1);
-        const T* base = in + idx - ii * st;
-        const T* S = Sdir[c * 3 + d];
-        T acc = 0;
-        if (d == c) {
-#pragma unroll
-            for (int j = 0; j < NC; ++j) acc += (TR ? S[j * NC + ii] : S[ii * NC + j]) * base[j * st];
-        } else {
-#pragma unroll
-            for (int j = 0; j < ND; ++j) acc += (TR ? S[j * ND + ii] : S[ii * ND + j]) * base[j * st];
-        }
+        const int ii = code_i(code, D);
+        T acc;
+        if (c == 0) acc = contract_entry<K, T, TR, 0, D>(in, idx, ii, Sdir[0 * 3 + D]);
+        else if (c == 1) acc = contract_entry<K, T, TR, 1, D>(in, idx, ii, Sdir[1 * 3 + D]);
+        else acc = contract_entry<K, T, TR, 2, D>(in, idx, ii, Sdir[2 * 3 + D]);
         out[idx] = acc;
     }
 }
@@ -208,11 +216,11 @@ __device__ inline void fd_inverse(T* v, T* w, const T* const* Sdir, const T* con
     // lanes read with unit stride (the lines' strided FP64 reads conflict in the
     // LDS banks and measured slower)
     if constexpr (sizeof(T) == 8) {
-        contract3<K, NTP, T, true>(v, w, 0, Sdir, codes);
+        contract3<K, NTP, T, true, 0>(v, w, Sdir, codes);
         __syncthreads();
-        contract3<K, NTP, T, true>(w, v, 1, Sdir, codes);
+        contract3<K, NTP, T, true, 1>(w, v, Sdir, codes);
         __syncthreads();
-        contract3<K, NTP, T, true>(v, w, 2, Sdir, codes);
+        contract3<K, NTP, T, true, 2>(v, w, Sdir, codes);
     } else {
         contract_lines<K, NTP, T, true, 0>(v, w, Sdir);
         __syncthreads();
@@ -227,11 +235,11 @@ __device__ inline void fd_inverse(T* v, T* w, const T* const* Sdir, const T* con
     }
     __syncthreads();
     if constexpr (sizeof(T) == 8) {
-        contract3<K, NTP, T, false>(w, v, 2, Sdir, codes);
+        contract3<K, NTP, T, false, 2>(w, v, Sdir, codes);
         __syncthreads();
-        contract3<K, NTP, T, false>(v, w, 1, Sdir, codes);
+        contract3<K, NTP, T, false, 1>(v, w, Sdir, codes);
         __syncthreads();
-        contract3<K, NTP, T, false>(w, v, 0, Sdir, codes);
+        contract3<K, NTP, T, false, 0>(w, v, Sdir, codes);
     } else {
         contract_lines<K, NTP, T, false, 2>(w, v, Sdir);
         __syncthreads();
