@@ -42,11 +42,7 @@ hipError_t launch(void* x, const void* r, const void* ptab, int n, int colour, d
         case 64: return launch_nt<K, T, 64>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
         case 128: return launch_nt<K, T, 128>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
         case 256: return launch_nt<K, T, 256>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
-        default: {
-            // measured: two waves for FP32 at k = 3, else PatchShape's default
-            constexpr int def = (K == 3 && sizeof(T) == 4) ? 128 : 0;
-            return launch_nt<K, T, def>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
-        }
+        default: return launch_nt<K, T, 0>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
     }
 }
 

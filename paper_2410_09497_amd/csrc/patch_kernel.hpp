@@ -21,8 +21,7 @@
 namespace smg {
 
 // threads per patch: NT_OVERRIDE if positive, else by degree (measured on
-// MI355X: one wave for k = 1, two for k = 2, four for k = 3; the launcher
-// picks two for FP32 at k = 3)
+// MI355X: one wave for k = 1, two for k = 2, four for k = 3)
 template <int K, int NT_OVERRIDE = 0>
 struct PatchShape {
     static constexpr int M = K + 1;
@@ -151,102 +150,29 @@ __device__ inline void contract3(const T* in, T* out, const T* const* Sdir, cons
     }
 }
 
-// Line form of contract3 along direction D: one thread per 1D line of a
-// component's box (the line along D through fixed indices of the two other
-// directions).  The thread loads the line once into registers and writes the
-// whole contracted line: n reads and n writes per line instead of n^2 reads.
-template <int K, int NTP, typename T, bool TR, int D>
-__device__ inline void contract_lines(const T* in, T* out, const T* const* Sdir) {
-    using P = PatchShape<K, NTP>;
-    constexpr int NV = P::NV, NC = P::NC, ND = P::ND;
-    // lines per component: NV / (extent along D); the component whose continuous direction is D has NC
-    constexpr int LC = NV / NC, LD = NV / ND;
-    constexpr int L0 = D == 0 ? LC : LD, L1 = D == 1 ? LC : LD, L2 = D == 2 ? LC : LD;
-    for (int l = threadIdx.x; l < L0 + L1 + L2; l += P::NT) {
-        const int c = l < L0 ? 0 : (l < L0 + L1 ? 1 : 2);
-        const int lc = l - (c == 0 ? 0 : (c == 1 ? L0 : L0 + L1));
-        const int e0 = c == 0 ? NC : ND, e1 = c == 1 ? NC : ND;
-        int base, st;
-        if constexpr (D == 0) {
-            base = lc * e0;            // (i1, i2) -> i1 e0 + i2 e0 e1 = lc e0
-            st = 1;
-        } else if constexpr (D == 1) {
-            const int i0 = lc % e0, i2 = lc / e0;
-            base = i0 + i2 * e0 * e1;
-            st = e0;
-        } else {
-            base = lc;                 // (i0, i1) -> i0 + i1 e0 = lc
-            st = e0 * e1;
-        }
-        const T* src = in + c * NV + base;
-        T* dst = out + c * NV + base;
-        const T* S = Sdir[c * 3 + D];
-        if (c == D) {
-            T v[NC];
-#pragma unroll
-            for (int j = 0; j < NC; ++j) v[j] = src[j * st];
-#pragma unroll
-            for (int i = 0; i < NC; ++i) {
-                T acc = 0;
-#pragma unroll
-                for (int j = 0; j < NC; ++j) acc += (TR ? S[j * NC + i] : S[i * NC + j]) * v[j];
-                dst[i * st] = acc;
-            }
-        } else {
-            T v[ND];
-#pragma unroll
-            for (int j = 0; j < ND; ++j) v[j] = src[j * st];
-#pragma unroll
-            for (int i = 0; i < ND; ++i) {
-                T acc = 0;
-#pragma unroll
-                for (int j = 0; j < ND; ++j) acc += (TR ? S[j * ND + i] : S[i * ND + j]) * v[j];
-                dst[i * st] = acc;
-            }
-        }
-    }
-}
-
 // v <- A^{-1} v for the three components (in place), work buffer w
 template <int K, int NTP, typename T>
 __device__ inline void fd_inverse(T* v, T* w, const T* const* Sdir, const T* const* Ldir, const int* codes) {
     using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV;
-    // FP32: a thread per line (fewer LDS reads); FP64: a thread per entry, whose
-    // lanes read with unit stride (the lines' strided FP64 reads conflict in the
-    // LDS banks and measured slower)
-    if constexpr (sizeof(T) == 8) {
-        contract3<K, NTP, T, true, 0>(v, w, Sdir, codes);
-        __syncthreads();
-        contract3<K, NTP, T, true, 1>(w, v, Sdir, codes);
-        __syncthreads();
-        contract3<K, NTP, T, true, 2>(v, w, Sdir, codes);
-    } else {
-        contract_lines<K, NTP, T, true, 0>(v, w, Sdir);
-        __syncthreads();
-        contract_lines<K, NTP, T, true, 1>(w, v, Sdir);
-        __syncthreads();
-        contract_lines<K, NTP, T, true, 2>(v, w, Sdir);
-    }
+    // a thread per entry: lanes read with unit stride (a thread per 1D line reads
+    // fewer words but with strided, bank-conflicting lanes, and measured slower)
+    contract3<K, NTP, T, true, 0>(v, w, Sdir, codes);
+    __syncthreads();
+    contract3<K, NTP, T, true, 1>(w, v, Sdir, codes);
+    __syncthreads();
+    contract3<K, NTP, T, true, 2>(v, w, Sdir, codes);
     __syncthreads();
     for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
         const int code = codes[idx], c = code_c(code);
         w[idx] /= Ldir[c * 3 + 0][code_i(code, 0)] + Ldir[c * 3 + 1][code_i(code, 1)] + Ldir[c * 3 + 2][code_i(code, 2)];
     }
     __syncthreads();
-    if constexpr (sizeof(T) == 8) {
-        contract3<K, NTP, T, false, 2>(w, v, Sdir, codes);
-        __syncthreads();
-        contract3<K, NTP, T, false, 1>(v, w, Sdir, codes);
-        __syncthreads();
-        contract3<K, NTP, T, false, 0>(w, v, Sdir, codes);
-    } else {
-        contract_lines<K, NTP, T, false, 2>(w, v, Sdir);
-        __syncthreads();
-        contract_lines<K, NTP, T, false, 1>(v, w, Sdir);
-        __syncthreads();
-        contract_lines<K, NTP, T, false, 0>(w, v, Sdir);
-    }
+    contract3<K, NTP, T, false, 2>(w, v, Sdir, codes);
+    __syncthreads();
+    contract3<K, NTP, T, false, 1>(v, w, Sdir, codes);
+    __syncthreads();
+    contract3<K, NTP, T, false, 0>(w, v, Sdir, codes);
     __syncthreads();
 }
 
