@@ -88,6 +88,27 @@ def test_fgmres_history_matches_oracle(n, k):
     assert rel_err(xg, S.normalize_pressure(xo)) <= 1e-6
 
 
+@pytest.mark.parametrize("restart", [1, 2])
+def test_fgmres_restart_matches_oracle(restart):
+    """Restarted FGMRES(1) and FGMRES(2): the restart path (true residual
+    recomputed, new Arnoldi basis) against the oracle's restarted FGMRES."""
+    torch = need_gpu()
+    n, k = 8, 1
+    mg_o = Multigrid(n, k)
+    S, K = mg_o.fine["S"], mg_o.fine["K"]
+    b = S.rhs(mf.sine_f, mf.sine_u)
+    xo, hist_o = fgmres(lambda v: K @ v, b, lambda v: mg_o.vcycle(v), rtol=1e-8, restart=restart)
+    announce("fgmres restart", f"n={n} k={k} restart={restart}")
+    mg = StokesMG(n, k, cg_rtol=1e-14, cg_max_it=500)
+    x, info = mg.solve(torch.from_numpy(b).cuda(), rtol=1e-8, restart=restart)
+    assert info["iterations"] == len(hist_o) - 1 and info["iterations"] > restart
+    h = np.array(info["history"])
+    ho = np.array(hist_o)
+    assert np.all(np.abs(np.log10(h[1:]) - np.log10(ho[1:])) <= 1e-4), (h, ho)
+    assert info["rel_residual"] <= 1e-8
+    assert rel_err(x.cpu().numpy(), S.normalize_pressure(xo)) <= 1e-6
+
+
 @pytest.mark.parametrize("k", [1, 2])
 def test_solve_f32_vcycle_reaches_tolerance(k):
     """Mixed precision (Sec. 4.3): FP32 V-cycle in FP64 FGMRES, to 1e-8."""
