@@ -453,8 +453,7 @@ __global__ void __launch_bounds__(256) patch_gather_kernel(const T* __restrict__
     __shared__ double red[256];
     int v[3];
     patch_vertex(g, p0 + blockIdx.x, v);
-    const double h = 1.0 / g.n, ih = g.n, ih2 = double(g.n) * g.n;
-    (void)h;
+    const double ih = g.n, ih2 = double(g.n) * g.n;
     double acc = 0.0;
     for (int q = threadIdx.x; q < g.size; q += 256) {
         bool pres;
