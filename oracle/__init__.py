@@ -21,7 +21,11 @@ Everything is computed from the plain definitions, in float64:
                   Sec. 3.2 written out with dense matrices.
 * ``mg``       -- transfers, the colourized vertex-patch smoother (Alg. 2),
                   the V-cycle (Sec. 3) and right-preconditioned FGMRES.
+* ``mlp``      -- the per-patch network of the learned local solver (not in
+                  the paper): forward, loss, backward, Adam, and smoother
+                  callbacks for pair capture and learned solves.
 
-Readings of passages where the paper is silent or garbled are listed in
-the design doc at the repository root (the file that documents the whole build).
+Where the paper is silent or garbled, each module states the reading it
+applies next to the code that applies it (bases and quadrature, the sign of
+B, the penalty and face terms, the restriction, the pseudo-inverse).
 """
