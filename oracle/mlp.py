@@ -126,3 +126,20 @@ def capture_local(mg, sink, level):
             sink.append((x, t))
         return upd
     return local
+
+
+def fallback_step(history, rho_ref):
+    """Contraction monitor of the learned local solver (not in the paper; the
+    exact solver is the fallback).  history[0] = 1 and history[n] is the
+    relative residual after outer step n.  The monitor looks at the
+    contraction rho_n = history[n] / history[n-1] of every step and returns
+    the first n at which it hands the rest of the solve to the exact local
+    solver, or -1 if it never does.  The bound is max(2 rho_ref, 1e-3) when a
+    reference contraction rho_ref > 0 of the plain method is known, else 1
+    (no progress); a contraction that is not finite also triggers."""
+    bound = max(2.0 * rho_ref, 1e-3) if rho_ref > 0 else 1.0
+    for n in range(1, len(history)):
+        rho = history[n] / history[n - 1] if history[n - 1] != 0 else float("nan")
+        if not (rho < bound):
+            return n
+    return -1
