@@ -19,9 +19,12 @@ FP32 V-cycle (mixed precision), and FP32 V-cycle with the learned local
 solver (trained first on ~10^6 pairs captured from exact V-cycles on 32^3
 cells with random smooth right-hand sides) with the exact-solver fallback.
 
+Third part, `c1`: the operator and the smoother for every degree k = 1..5 in
+FP64 and FP32 at 64^3 cells (K applications and a few sweeps per cell).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 2] [--n 64]
                        [--dtype f64|f32] [--no-cpu-baseline] [--no-solve]
-                       [--solve-n 128]
+                       [--solve-n 128] [--no-c1] [--c1-sweeps 3]
 """
 import argparse
 import hashlib
@@ -93,6 +96,57 @@ def cpu_baseline(k):
             "sample": f"oracle stokes apply (local element matrices, NumPy FP64) on {n}^3 cells, k={k} "
                       f"({S.ndof} unknowns), {reps} repetitions, {el:.1f} s; host has "
                       f"{len(os.sched_getaffinity(0))} usable cores"}
+
+
+def c1_section(dev, n, steps, sweeps, log):
+    """Every degree and precision of the plain method at scale: the operator
+    (steps applications, HIP events on the launch stream, rotating pairs over
+    512 MB) and the smoother (sweeps of patch_smooth from x = 0 on a random
+    right-hand side, local CG rtol 1e-3 / at most 15 iterations)."""
+    import torch
+    from paper_2410_09497_amd import StokesMG
+    from paper_2410_09497_amd.synth import uniform_vector
+    out = {"workload": f"{n}^3 cells, RT_k/DG Q_k, k = 1..5, FP64 and FP32; x ~ U[-1,1] PCG64 seed k; "
+                       f"{steps} stokes_apply calls and {sweeps} patch_smooth sweeps per cell of the table"}
+    stream = torch.cuda.current_stream(dev)
+    for k in range(1, 6):
+        mg = StokesMG(n, k, n_levels=1, cg_rtol=1e-3, cg_max_it=15, device=dev)
+        ndof = mg.ndof()
+        x64 = torch.from_numpy(uniform_vector(ndof, seed=k)).to(dev)
+        for dt, es in (("f64", 8), ("f32", 4)):
+            x0 = x64 if dt == "f64" else x64.float()
+            npairs = max(1, -(-512 * 2 ** 20 // (2 * ndof * es)))
+            xs = [x0.clone() for _ in range(npairs)]
+            ys = [torch.empty_like(x0) for _ in range(npairs)]
+            for i in range(3):
+                mg.apply(xs[i % npairs], ys[i % npairs])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i in range(steps):
+                mg.apply(xs[i % npairs], ys[i % npairs])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_apply = e0.elapsed_time(e1) * 1e-3 / steps
+            del xs, ys
+            b = x0.clone()
+            xsm = torch.zeros_like(x0)
+            mg.smooth(xsm, b, sweeps=1)
+            mg.cg_stats(reset=True)
+            xsm.zero_()
+            e0.record(stream)
+            mg.smooth(xsm, b, sweeps=sweeps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_sweep = e0.elapsed_time(e1) * 1e-3 / sweeps
+            its, solves = mg.cg_stats(reset=True)
+            out[f"k{k}_{dt}"] = {"unknowns": ndof, "apply_ms": t_apply * 1e3, "apply_GDoF_s": ndof / t_apply / 1e9,
+                                 "apply_hbm_frac": 2 * es * ndof / t_apply / 1e9 / HBM_PEAK_GBS,
+                                 "sweep_ms": t_sweep * 1e3, "sweep_GDoF_s": ndof / t_sweep / 1e9,
+                                 "sweep_avg_local_cg": its / max(solves, 1)}
+            log(f"[bench] C1 k={k} {dt}: apply {t_apply * 1e3:.3f} ms, sweep {t_sweep * 1e3:.1f} ms")
+        del mg, x64
+        torch.cuda.empty_cache()
+    return out
 
 
 def solve_section(dev, k, n_solve, log):
@@ -170,7 +224,13 @@ def solve_section(dev, k, n_solve, log):
     log(f"[bench] learned_mg: {info['seconds']:.3f} s, {info['iterations']} iterations, fallback after {fb}")
     out.update(runs)
     out["fp32_speedup_vs_fp64"] = runs["fp64_mg"]["seconds"] / runs["fp32_mg"]["seconds"]
-    out["learned_speedup_vs_fp64"] = runs["fp64_mg"]["seconds"] / runs["learned_mg"]["seconds"]
+    # a learned speed-up exists only when every step used the network (the fallback never fired)
+    runs["learned_mg"]["learned_steps_used"] = info["iterations"] if fb < 0 else fb
+    out["learned_speedup_vs_fp64"] = (runs["fp64_mg"]["seconds"] / runs["learned_mg"]["seconds"]
+                                      if fb < 0 else None)
+    if fb >= 0:
+        out["learned_note"] = (f"the contraction monitor handed the solve to the exact local solver after "
+                               f"{fb} learned step(s); the learned variant gains nothing on this problem")
     del mg
     torch.cuda.empty_cache()
     return out
@@ -187,6 +247,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--solve-n", type=int, default=128)
+    ap.add_argument("--no-c1", action="store_true")
+    ap.add_argument("--c1-sweeps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the method's hot path here is single-GPU "
@@ -273,6 +335,8 @@ def main():
     del xs, ys, cbuf_a, cbuf_b, mg
     torch.cuda.empty_cache()
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    if not args.no_c1:
+        out["c1"] = c1_section(dev, args.n, args.steps, args.c1_sweeps, log)
     if not args.no_solve:
         out["solve"] = solve_section(dev, k, args.solve_n, log)
     if not args.no_cpu_baseline:

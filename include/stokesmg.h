@@ -69,7 +69,9 @@ typedef struct {
     double penalty_factor;  /* gamma = penalty_factor (k+1)^2 / h; must be 2.0, the method's value
                                (the kernels carry it as a compile-time constant): other values
                                return STOKESMG_EUNSUPPORTED */
-    double cg_rtol;         /* local Schur-complement CG: stop when ||r|| <= cg_rtol ||r_0|| ... */
+    double cg_rtol;         /* local Schur-complement CG: stop when ||r|| <= cg_rtol ||r_0|| (a value
+                               below 16 eps of the arithmetic -- 1.9e-6 in FP32, 3.6e-15 in FP64 --
+                               is raised to it; the iteration also stops if d.Sd <= 0) ... */
     int    cg_max_it;       /* ... or after cg_max_it iterations (Sec. 3.3: about 15 on average) */
 } stokesmg_config;
 
@@ -123,7 +125,7 @@ int stokes_residual(stokesmg_t* h, int level, int dtype, const void* b, const vo
  * A_j^{-1} applied by fast diagonalization; with a tight cg_rtol it equals the
  * pseudo-inverse solve (Sec. 3.3).  x is updated in place; b is read only.
  * x and b must not overlap each other or the workspace (EINVAL).
- * Degrees 1..3 (EUNSUPPORTED otherwise). */
+ * Degrees 1..5. */
 int patch_smooth(stokesmg_t* h, int level, int dtype, void* x, const void* b, int n_sweeps, void* stream);
 
 /* Total local CG iterations and local solves performed by patch_smooth since
@@ -154,9 +156,12 @@ typedef struct {
                                  took over for the rest of the solve (-1: never) */
 } stokesmg_info;
 
-/* Bytes of the caller-owned solve workspace for FGMRES(restart), 1 <= restart <= 60:
- * (2 restart + 4) FP64 vectors of the finest level. */
-int stokesmg_solve_workspace_size(const stokesmg_t* h, int restart, size_t* bytes);
+/* Bytes of the caller-owned solve workspace for FGMRES(restart), 1 <= restart <= 60,
+ * with the V-cycle in vcycle_dtype: restart + 1 FP64 Krylov vectors V, restart
+ * preconditioned vectors Z in the V-cycle's precision (FP32 for an FP32 cycle),
+ * and three more finest-level vectors.  solve() uses a shorter restart when the
+ * workspace it is given holds fewer vectors (at least one step must fit). */
+int stokesmg_solve_workspace_size(const stokesmg_t* h, int restart, int vcycle_dtype, size_t* bytes);
 
 /* Solves K x = b on the finest level by right-preconditioned restarted FGMRES
  * (GMRES preconditioned by the V-cycle, Sec. 3.3), x_0 = 0, until the

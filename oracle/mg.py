@@ -75,13 +75,13 @@ def prolongation(Sc, Sf):
 class Multigrid:
     """Level hierarchy n = 1, 2, 4, ..., n_fine (or from ``n_coarse``)."""
 
-    def __init__(self, n_fine, k, n_coarse=1, penalty_factor=2.0):
+    def __init__(self, n_fine, k, n_coarse=1, penalty_factor=2.0, local_solver="pinv"):
         self.levels = []
         n = n_coarse
         while n <= n_fine:
             S = Stokes(n, k, penalty_factor)
             K = S.assemble()
-            Pt = Patches(S) if n >= 2 else None
+            Pt = Patches(S, local_solver) if n >= 2 else None
             self.levels.append(dict(S=S, K=K, patches=Pt))
             n *= 2
         assert self.levels[-1]["S"].n == n_fine, "n_fine must be n_coarse * 2^L"

@@ -177,13 +177,15 @@ class StokesMG:
         if x is None:
             x = torch.empty_like(b)
         nb = ctypes.c_size_t()
-        self._check(_lib.lib.stokesmg_solve_workspace_size(self._h, restart, ctypes.byref(nb)))
+        vd = F64 if vcycle_dtype == "f64" else F32
+        # the basis never needs more vectors than steps
+        m = min(restart, max_it)
+        self._check(_lib.lib.stokesmg_solve_workspace_size(self._h, m, vd, ctypes.byref(nb)))
         ws = getattr(self, "_solve_ws", None)
         if ws is None or ws.numel() < nb.value:
             self._solve_ws = None
             ws = self._solve_ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
         info = _lib.Info()
-        vd = F64 if vcycle_dtype == "f64" else F32
         rc = _lib.lib.solve(self._h, b.data_ptr(), x.data_ptr(), rtol, max_it, restart, vd, ws.data_ptr(),
                             ws.numel(), ctypes.byref(info), self._stream())
         if rc != 0 and not (allow_notconv and rc == _lib.ENOTCONV):

@@ -52,7 +52,7 @@ def _load():
         "patch_smooth": (i32, [vp, i32, i32, vp, vp, i32, vp]),
         "stokesmg_cg_stats": (i32, [vp, i64p, i64p, i32, vp]),
         "vcycle": (i32, [vp, i32, vp, vp, vp]),
-        "stokesmg_solve_workspace_size": (i32, [vp, i32, szp]),
+        "stokesmg_solve_workspace_size": (i32, [vp, i32, i32, szp]),
         "solve": (i32, [vp, vp, vp, ctypes.c_double, i32, i32, i32, vp, ctypes.c_size_t, ctypes.POINTER(Info), vp]),
         "stokesmg_rhs_manufactured": (i32, [vp, i32, i32, vp, vp]),
         "stokesmg_rhs_fourier": (i32, [vp, i32, i32, vp, vp, vp, vp, vp]),

@@ -8,7 +8,6 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build", "obj")
-GEN = os.path.join(ROOT, "_build", "gen")
 LIB = os.path.join(PKG, "libstokesmg.so")
 
 SOURCES = ["api.cpp", "tables.cpp", "apply.hip", "apply_common.cpp", "apply_k1.hip", "apply_k2.hip", "apply_k3.hip",
@@ -18,21 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # never form packed FP32 arithmetic (v_pk_*_f32)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", GEN]
-
-
-def _generate_tables():
-    """Compiles and runs the host generator of the constexpr reference tables."""
-    os.makedirs(GEN, exist_ok=True)
-    exe = os.path.join(GEN, "gen_ref_tables")
-    cxx = os.environ.get("CXX", "g++")
-    p = subprocess.run([cxx, "-O2", "-std=c++17", "-o", exe, os.path.join(CSRC, "gen_ref_tables.cpp")],
-                       capture_output=True, text=True)
-    if p.returncode != 0:
-        raise RuntimeError(f"table generator build failed:\n{p.stdout}\n{p.stderr}")
-    p = subprocess.run([exe, os.path.join(GEN, "ref_tables_gen.hpp")], capture_output=True, text=True)
-    if p.returncode != 0:
-        raise RuntimeError(f"table generator failed:\n{p.stdout}\n{p.stderr}")
+         "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 
 def _compile(src):
@@ -46,7 +31,6 @@ def _compile(src):
 
 def build(verbose=True):
     os.makedirs(OBJ, exist_ok=True)
-    _generate_tables()
     jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))

@@ -215,7 +215,6 @@ int patch_smooth(stokesmg_t* h, int level, int dtype, void* x, const void* b, in
     if (int rc = check_level_dtype(h, level, dtype)) return rc;
     if (!x || !b || n_sweeps < 0) return h->fail(STOKESMG_EINVAL, "null vector or negative sweep count");
     if (h->lv[level].n < 2) return h->fail(STOKESMG_EINVAL, "level has no interior vertex (n < 2)");
-    if (h->cfg.k > 3) return h->fail(STOKESMG_EUNSUPPORTED, "patch_smooth is built for degrees 1..3");
     const size_t es = dtype == STOKESMG_F64 ? 8 : 4;
     const size_t bytes = size_t(level_total(h, level)) * es;
     if (overlap(x, b, bytes) || ranges_overlap(x, bytes, h->ws, h->ws_bytes) ||

@@ -15,9 +15,7 @@ template <int K>
 hipError_t launch_apply_k(bool f64, bool resid, const void* x, const void* b, void* y, const void* tab, int n,
                           hipStream_t st);
 
-// cell layers per workgroup along z (per degree; STOKESMG_APPLY_CZ overrides), for the
-// tile kernels and for the wave-per-position kernel
+// cell layers per workgroup along z for the tile kernels (per degree and level size)
 int apply_chunk_layers(int k, int n, int blocks_xy);
-int apply_chunk_layers_position(int n, int blocks_xy);
 
 }  // namespace smg

@@ -3,11 +3,8 @@
 
 #include <algorithm>
 #include <cstdio>
-#include <cstdlib>
-#include <cstring>
 
 #include "apply.hpp"
-#include "apply2_kernel.hpp"
 #include "apply3_kernel.hpp"
 #include "apply_kernel.hpp"
 
@@ -49,56 +46,17 @@ hipError_t launch_split(const void* x, const void* b, void* y, const void* tab, 
     return hipGetLastError();
 }
 
-template <int K, typename T, bool RESID>
-hipError_t launch_wave_position(const void* x, const void* b, void* y, int n, hipStream_t st) {
-    using S = Ap2<K>;
-    const int tiles = (n + S::C - 1) / S::C;
-    const int cz = apply_chunk_layers_position(n, tiles * tiles);
-    const int nzc = (n + cz - 1) / cz;
-    hipLaunchKernelGGL((apply2_kernel<K, T, RESID>), dim3(tiles * tiles * nzc), dim3(S::NT), 0, st,
-                       static_cast<const T*>(x), static_cast<const T*>(b), static_cast<T*>(y), n, cz, tiles,
-                       T(1.0 / n));
-    return hipGetLastError();
-}
-
-// Kernel choice.  Defaults are the fastest measured on MI355X at 64^3 cells
-// (HBM-resident); STOKESMG_APPLY_KERNEL = generic | pipelined | position | split
-// overrides them for comparison runs.
-struct ApplyChoice {
-    int kernel = 0;   // 0 default, 1 generic, 2 generic with pipelined loads, 3 wave per position, 4 split groups
-};
-inline ApplyChoice apply_choice() {
-    static const ApplyChoice c = [] {
-        ApplyChoice r;
-        if (const char* s = std::getenv("STOKESMG_APPLY_KERNEL")) {
-            if (!std::strcmp(s, "generic")) r.kernel = 1;
-            else if (!std::strcmp(s, "pipelined")) r.kernel = 2;
-            else if (!std::strcmp(s, "position")) r.kernel = 3;
-            else if (!std::strcmp(s, "split")) r.kernel = 4;
-        }
-        return r;
-    }();
-    return c;
-}
-
-// measured defaults per degree and precision
-template <int K> constexpr bool position_default(bool f64) { return K == 1 && !f64; }
+// Kernel choice per degree and precision: the fastest measured on MI355X at
+// 64^3 cells (HBM-resident).  The split kernel serves degrees 2, 3, 5 and
+// FP32 at degree 4; the single-group kernel with pipelined plane loads
+// serves degree 1 and FP64 at degree 4.
 // (degree 2 also compared 8x4, 6x4, 7x3 and 5x5 tiles and 16-layer chunks for the split kernel: all slower)
 template <int K> constexpr bool split_default(bool f64) { return K == 2 || K == 3 || K == 5 || (K == 4 && !f64); }
-template <int K> constexpr bool pipelined_default(bool f64) { return K <= 4 || !f64; }
 
 template <int K, typename T, bool R>
 hipError_t launch_degree_t(bool f64, const void* x, const void* b, void* y, const void* tab, int n, hipStream_t st) {
-    const ApplyChoice c = apply_choice();
-    // the wave-per-position kernel is wrong in FP64 at degree 3: never used there
-    const bool position = (c.kernel == 3 || (c.kernel == 0 && position_default<K>(f64))) && !(K == 3 && f64);
-    // the wave-per-position kernel is built for degrees 1..3 only
-    if constexpr (K <= 3)
-        if (position) return launch_wave_position<K, T, R>(x, b, y, n, st);
-    if (c.kernel == 4 || (c.kernel == 0 && split_default<K>(f64))) return launch_split<K, T, R>(x, b, y, tab, n, st);
-    const bool pf = c.kernel == 2 || (c.kernel == 0 && pipelined_default<K>(f64));
-    return pf ? launch_generic<K, T, R, TileOf<K>::CX, TileOf<K>::CY, true>(x, b, y, tab, n, st)
-              : launch_generic<K, T, R, TileOf<K>::CX, TileOf<K>::CY, false>(x, b, y, tab, n, st);
+    if (split_default<K>(f64)) return launch_split<K, T, R>(x, b, y, tab, n, st);
+    return launch_generic<K, T, R, TileOf<K>::CX, TileOf<K>::CY, true>(x, b, y, tab, n, st);
 }
 
 template <int K>

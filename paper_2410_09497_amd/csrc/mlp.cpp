@@ -179,12 +179,13 @@ int mlp_interior_solve(stokesmg* h, int level, bool f64, void* x, const void* r,
     return STOKESMG_OK;
 }
 
-int smooth_sweep(stokesmg* h, int level, bool f64, void* x, const void* b, hipStream_t st, const Capture* cap) {
+int smooth_sweep(stokesmg* h, int level, bool f64, void* x, const void* b, hipStream_t st, const Capture* cap,
+                 void* r_in, int* counters_in, bool own_counters) {
     const int n = h->lv[level].n, k = h->cfg.k;
     const void* tab = h->ws + (f64 ? h->tab_f64[level] : h->tab_f32[level]);
     const void* ptab = h->ws + (f64 ? h->ptab_f64[level] : h->ptab_f32[level]);
-    void* r = h->ws + h->r_vec;
-    int* counters = reinterpret_cast<int*>(h->ws + h->cg_counter);
+    void* r = r_in ? r_in : h->ws + h->r_vec;
+    int* counters = own_counters ? counters_in : reinterpret_cast<int*>(h->ws + h->cg_counter);
     const bool learned = h->local_solver == STOKESMG_LOCAL_MLP && !cap;
     const size_t N = size_t(level_total(h, level));
     for (int c = 0; c < 8; ++c) {

@@ -21,7 +21,11 @@ struct Capture {
 // one sweep of the colourized smoother on `level`: per colour the residual,
 // then the local solves (exact; learned on interior patches with the MLP
 // solver; exact with pair capture when `cap` is given)
-int smooth_sweep(stokesmg* h, int level, bool f64, void* x, const void* b, hipStream_t st, const Capture* cap);
+// One sweep of Alg. 2.  The residual vector and the CG counters come from the
+// workspace unless `r` / `counters` are given (the no-allocation entry point
+// passes its static scratch; counters may then be null).
+int smooth_sweep(stokesmg* h, int level, bool f64, void* x, const void* b, hipStream_t st, const Capture* cap,
+                 void* r = nullptr, int* counters = nullptr, bool own_counters = false);
 
 // the learned correction of every interior patch of one colour
 int mlp_interior_solve(stokesmg* h, int level, bool f64, void* x, const void* r, int colour, hipStream_t st);

@@ -1,8 +1,6 @@
 // Launcher of the vertex-patch local solves (one workgroup per patch of a colour).
 #include "patch.hpp"
 
-#include <cstdlib>
-
 #include "patch_kernel.hpp"
 
 namespace smg {
@@ -29,21 +27,11 @@ hipError_t launch_nt(void* x, const void* r, const void* ptab, int n, int colour
     return hipGetLastError();
 }
 
-// threads per patch: the degree's default (PatchShape), or STOKESMG_PATCH_THREADS = 64 | 128 | 256
-// for comparison runs
+// threads per patch: the degree's default (PatchShape)
 template <int K, typename T>
 hipError_t launch(void* x, const void* r, const void* ptab, int n, int colour, double rtol, int maxit, int* counters,
                   bool bonly, hipStream_t st) {
-    static const int threads = [] {
-        const char* s = std::getenv("STOKESMG_PATCH_THREADS");
-        return s ? std::atoi(s) : 0;
-    }();
-    switch (threads) {
-        case 64: return launch_nt<K, T, 64>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
-        case 128: return launch_nt<K, T, 128>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
-        case 256: return launch_nt<K, T, 256>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
-        default: return launch_nt<K, T, 0>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
-    }
+    return launch_nt<K, T, 0>(x, r, ptab, n, colour, rtol, maxit, counters, bonly, st);
 }
 
 }  // namespace
@@ -57,6 +45,10 @@ hipError_t launch_patch_solve(int k, bool f64, void* x, const void* r, const voi
                            : launch<2, float>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st);
         case 3: return f64 ? launch<3, double>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st)
                            : launch<3, float>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st);
+        case 4: return f64 ? launch<4, double>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st)
+                           : launch<4, float>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st);
+        case 5: return f64 ? launch<5, double>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st)
+                           : launch<5, float>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st);
         default: return hipErrorInvalidValue;
     }
 }

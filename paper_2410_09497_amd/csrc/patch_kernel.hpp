@@ -21,14 +21,17 @@
 namespace smg {
 
 // threads per patch: NT_OVERRIDE if positive, else by degree (measured on
-// MI355X: one wave for k = 1, two for k = 2, four for k = 3)
+// MI355X: one wave for k = 1, two for k = 2, four for k = 3 and 4, eight for
+// k = 5, whose patch vectors take most of a CU's LDS so one workgroup runs
+// per CU).  LDS per workgroup: 2 velocity-sized and 4 pressure-sized arrays
+// and the entry table, 86 KB at k = 4 and 150 KB at k = 5 in FP64.
 template <int K, int NT_OVERRIDE = 0>
 struct PatchShape {
     static constexpr int M = K + 1;
     static constexpr int NC = 2 * K + 1, ND = 2 * K + 2;
     static constexpr int NV = NC * ND * ND;      // one velocity component
     static constexpr int NP = ND * ND * ND;      // pressure
-    static constexpr int NT = NT_OVERRIDE > 0 ? NT_OVERRIDE : (K == 1 ? 64 : (K == 2 ? 128 : 256));
+    static constexpr int NT = NT_OVERRIDE > 0 ? NT_OVERRIDE : (K == 1 ? 64 : (K == 2 ? 128 : (K <= 4 ? 256 : 512)));
     static constexpr int NW = NT / 64;           // waves
 };
 
@@ -332,8 +335,12 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
         rr = block_sum<NW>(s2, red);
     }
     const T rr0 = rr;
+    // CG in precision T cannot reduce the residual much below 16 eps: a tighter request is raised
+    // to that level (1.9e-6 in FP32, 3.6e-15 in FP64) instead of iterating on rounding noise
+    constexpr T kFloor = T(16) * (sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7));
+    const T rtol = cg_rtol > kFloor ? cg_rtol : kFloor;
     int it = 0;
-    while (it < cg_maxit && rr > cg_rtol * cg_rtol * rr0 && rr > T(0)) {
+    while (it < cg_maxit && rr > rtol * rtol * rr0 && rr > T(0)) {
         // Q = S Dv = B A^{-1} B^T Dv, projected to mean zero
         apply_BT<K, NTP, T>(Dv, V1, Dp, md, codes);
         __syncthreads();
@@ -346,6 +353,10 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
             dq += Dv[i] * Q[i];
         }
         block_sum2<NW>(s, dq, red);   // Dv has zero mean, so Dv . (Q - mean) = Dv . Q
+        // S is positive definite on mean-zero vectors; d.Sd <= 0 (or not finite) only comes from
+        // rounding once the iteration has stagnated at the working precision: stop there (the value
+        // is uniform over the workgroup, so every thread leaves together)
+        if (!(dq > T(0)) || !(dq < T(__builtin_inff()))) break;
         const T mean = s / T(NP);
         const T alpha = rr / dq;
         T s2 = 0;

@@ -56,7 +56,6 @@ int vcycle_level(stokesmg* h, int l, bool f64, const void* b, void* x, hipStream
 
 int check_mg(stokesmg* h) {
     if (!h->ws) return h->fail(STOKESMG_ENOMEM, "no workspace set");
-    if (h->cfg.k > 3) return h->fail(STOKESMG_EUNSUPPORTED, "the patch smoother is built for degrees 1..3");
     for (int l = 1; l < h->n_levels; ++l)
         if (h->lv[l].n < 2) return h->fail(STOKESMG_EINVAL, "level without interior vertices");
     if (h->coarse_pinv.empty()) return h->fail(STOKESMG_EUNSUPPORTED, "coarsest level too large for the dense solve");
@@ -152,41 +151,58 @@ int vcycle(stokesmg_t* h, int dtype, const void* b, void* x, void* stream) {
     return vcycle_level(h, L, dtype == STOKESMG_F64, b, x, static_cast<hipStream_t>(stream), nullptr);
 }
 
-int stokesmg_solve_workspace_size(const stokesmg_t* h, int restart, size_t* bytes) {
+namespace {
+// bytes of the solve workspace for FGMRES(m): V (m + 1 FP64 vectors), Z (m vectors in the V-cycle's
+// precision: the FP32 cycle's output is kept as it is produced), w, and the V-cycle's input plus an
+// FP64 copy of z_j (FP32 cycle) or its input and output (FP64 cycle)
+size_t solve_ws_bytes(size_t N, int m, bool f32) {
+    const size_t zs = f32 ? sizeof(float) : sizeof(double);
+    const size_t extra = f32 ? N * sizeof(float) + N * sizeof(double) : 2 * N * sizeof(double);
+    return size_t(m + 1) * N * sizeof(double) + size_t(m) * N * zs + N * sizeof(double) + extra + 256 + 3 * 256;
+}
+}  // namespace
+
+int stokesmg_solve_workspace_size(const stokesmg_t* h, int restart, int vcycle_dtype, size_t* bytes) {
     if (!h || !bytes || restart < 1 || restart > 60) return STOKESMG_EINVAL;
-    const size_t N = size_t(level_total(h, h->n_levels - 1));
-    // V: restart+1, Z: restart, w, V-cycle input and output: FP64 each
-    *bytes = (size_t(2 * restart + 4) * N) * sizeof(double) + 256;
+    if (vcycle_dtype != STOKESMG_F64 && vcycle_dtype != STOKESMG_F32) return STOKESMG_EINVAL;
+    *bytes = solve_ws_bytes(size_t(level_total(h, h->n_levels - 1)), restart, vcycle_dtype == STOKESMG_F32);
     return STOKESMG_OK;
 }
 
-int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, int restart, int vcycle_dtype,
-          void* solve_ws, size_t solve_ws_bytes, stokesmg_info* info, void* stream) {
+int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, int restart_in, int vcycle_dtype,
+          void* solve_ws, size_t solve_ws_bytes_in, stokesmg_info* info, void* stream) {
     if (!h) return STOKESMG_EINVAL;
     if (int rc = check_mg(h)) return rc;
-    if (!b || !x || !solve_ws || !(rtol > 0) || max_it < 1 || restart < 1 || restart > 60)
+    if (!b || !x || !solve_ws || !(rtol > 0) || max_it < 1 || restart_in < 1 || restart_in > 60)
         return h->fail(STOKESMG_EINVAL, "bad solve arguments");
     if (vcycle_dtype != STOKESMG_F64 && vcycle_dtype != STOKESMG_F32)
         return h->fail(STOKESMG_EINVAL, "vcycle dtype must be F64 or F32");
-    size_t need = 0;
-    stokesmg_solve_workspace_size(h, restart, &need);
-    if (solve_ws_bytes < need) return h->fail(STOKESMG_ENOMEM, "solve workspace too small");
+    const bool f32 = vcycle_dtype == STOKESMG_F32;
+    const int L = h->n_levels - 1;
+    const size_t N = size_t(level_total(h, L));
+    // the Krylov basis takes what the caller provided: restart is reduced to the largest length
+    // whose vectors fit (a caller expecting a few steps sizes the workspace for a few vectors)
+    int restart = restart_in;
+    while (restart >= 1 && solve_ws_bytes(N, restart, f32) > solve_ws_bytes_in) --restart;
+    if (restart < 1) return h->fail(STOKESMG_ENOMEM, "solve workspace too small for one Arnoldi step");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const auto t0 = std::chrono::steady_clock::now();
-    const int L = h->n_levels - 1;
     const int k = h->cfg.k, n = h->lv[L].n;
-    const size_t N = size_t(level_total(h, L));
     const size_t nb = N * sizeof(double);
-    if (ranges_overlap(b, nb, x, nb) || ranges_overlap(x, nb, solve_ws, solve_ws_bytes) ||
-        ranges_overlap(b, nb, solve_ws, solve_ws_bytes) || ranges_overlap(x, nb, h->ws, h->ws_bytes))
+    if (ranges_overlap(b, nb, x, nb) || ranges_overlap(x, nb, solve_ws, solve_ws_bytes_in) ||
+        ranges_overlap(b, nb, solve_ws, solve_ws_bytes_in) || ranges_overlap(x, nb, h->ws, h->ws_bytes))
         return h->fail(STOKESMG_EINVAL, "b, x and the workspaces must not overlap");
-    double* base = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(solve_ws) + 255) & ~uintptr_t(255));
-    double* V = base;                              // restart + 1 vectors
-    double* Z = V + size_t(restart + 1) * N;       // restart vectors
-    double* w = Z + size_t(restart) * N;
-    double* vin = w + N;                           // V-cycle input / output in its dtype
-    double* vout = vin + N;
-    const bool f32 = vcycle_dtype == STOKESMG_F32;
+    auto align = [](uintptr_t p) { return (p + 255) & ~uintptr_t(255); };
+    double* base = reinterpret_cast<double*>(align(reinterpret_cast<uintptr_t>(solve_ws)));
+    double* V = base;                              // restart + 1 FP64 vectors
+    unsigned char* zb = reinterpret_cast<unsigned char*>(V + size_t(restart + 1) * N);
+    const size_t zs = f32 ? sizeof(float) : sizeof(double);
+    double* w = reinterpret_cast<double*>(align(reinterpret_cast<uintptr_t>(zb + size_t(restart) * N * zs)));
+    // FP32 cycle: vin = FP32 input, z64 = FP64 copy of z_j; FP64 cycle: z_j is written in place, vin unused
+    void* vin = w + N;
+    double* z64 = reinterpret_cast<double*>(
+        align(reinterpret_cast<uintptr_t>(static_cast<unsigned char*>(vin) + N * (f32 ? sizeof(float) : sizeof(double)))));
+    auto zvec = [&](int j) -> void* { return zb + size_t(j) * N * zs; };
     const void* tab64 = h->ws + h->tab_f64[L];
     double* coef = reinterpret_cast<double*>(h->ws + h->scratch_off);   // device coefficients (<= 64)
     if (info) {
@@ -237,17 +253,20 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
         int jdone = 0;
         for (int j = 0; j < restart; ++j) {
             double* vj = V + size_t(j) * N;
-            double* zj = Z + size_t(j) * N;
-            // z_j = P^{-1} v_j (FP32 V-cycle: convert on entry and exit, the precision boundary)
+            // z_j = P^{-1} v_j (FP32 V-cycle: convert on entry and exit, the precision boundary; z_j
+            // stays FP32 in the basis and its FP64 copy feeds the FP64 operator)
+            double* zj64;
             if (f32) {
                 SMG_HIP(h, smg::launch_convert(true, vj, vin, N, st));
-                if (int rc = vcycle_level(h, L, false, vin, vout, st, nullptr)) return rc;
-                SMG_HIP(h, smg::launch_convert(false, vout, zj, N, st));
+                if (int rc = vcycle_level(h, L, false, vin, zvec(j), st, nullptr)) return rc;
+                SMG_HIP(h, smg::launch_convert(false, zvec(j), z64, N, st));
+                zj64 = z64;
             } else {
-                if (int rc = vcycle_level(h, L, true, vj, zj, st, nullptr)) return rc;
+                zj64 = static_cast<double*>(zvec(j));
+                if (int rc = vcycle_level(h, L, true, vj, zj64, st, nullptr)) return rc;
             }
             // w = K z_j, orthogonalized twice against V_0..V_j (classical Gram-Schmidt, twice)
-            SMG_HIP(h, smg::launch_apply(k, true, false, zj, nullptr, w, tab64, n, st));
+            SMG_HIP(h, smg::launch_apply(k, true, false, zj64, nullptr, w, tab64, n, st));
             if (int rc = host_dots(h, V, N, w, j + 1, N, hv.data(), st)) return rc;
             SMG_HIP(h, hipMemcpyAsync(coef, hv.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, st));
             SMG_HIP(h, smg::launch_multiaxpy(V, N, coef, j + 1, -1.0, 1.0, w, N, st));
@@ -313,7 +332,14 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
             y[i] = s / H[size_t(i) * restart + i];
         }
         SMG_HIP(h, hipMemcpyAsync(coef, y.data(), jdone * sizeof(double), hipMemcpyHostToDevice, st));
-        SMG_HIP(h, smg::launch_multiaxpy(Z, N, coef, jdone, 1.0, 1.0, x, N, st));
+        if (f32) {
+            for (int i = 0; i < jdone; ++i) {
+                SMG_HIP(h, smg::launch_convert(false, zvec(i), z64, N, st));
+                SMG_HIP(h, smg::launch_multiaxpy(z64, 0, coef + i, 1, 1.0, 1.0, x, N, st));
+            }
+        } else {
+            SMG_HIP(h, smg::launch_multiaxpy(static_cast<const double*>(zvec(0)), N, coef, jdone, 1.0, 1.0, x, N, st));
+        }
         SMG_HIP(h, hipStreamSynchronize(st));
         if (hist.back() <= rtol) conv = true;
     }

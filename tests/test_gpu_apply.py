@@ -52,11 +52,36 @@ def test_residual(n, k):
     assert rel_err(r32.double().cpu().numpy(), rref) <= 1e-5
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_apply_multi_tile_multi_chunk(k):
+    """16^3 cells, full vector: the launch splits the level into several xy
+    tiles (some ragged at k = 2, 5) and two z chunks, so the inter-tile and
+    inter-chunk halos are compared with the oracle; the residual form too."""
+    torch = need_gpu()
+    n = 16
+    mg = StokesMG(n, k, n_levels=1)
+    S = Stokes(n, k)
+    x = uniform_vector(S.ndof, seed=300 + k)
+    b = uniform_vector(S.ndof, seed=400 + k)
+    yref = S.apply(x)
+    announce("apply tiles+chunks", f"n={n} k={k}")
+    xd = torch.from_numpy(x).cuda()
+    bd = torch.from_numpy(b).cuda()
+    y = mg.apply(xd).cpu().numpy()
+    e, eu, ep = block_errs(S, y, yref)
+    assert e <= 1e-12 and eu <= 1e-12 and ep <= 1e-12, (k, e, eu, ep)
+    y32 = mg.apply(xd.float()).double().cpu().numpy()
+    e, eu, ep = block_errs(S, y32, yref)
+    assert e <= 1e-5 and eu <= 1e-5 and ep <= 1e-5, (k, e, eu, ep)
+    r = mg.residual(bd, xd).cpu().numpy()
+    assert rel_err(r, b - yref) <= 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 def test_apply_full_size_sampled_rows(k):
-    """64^3 cells (the benchmark size): rows sampled across the domain,
-    including the first and last rows of every block, computed one by one by
-    the oracle."""
+    """64^3 cells (the benchmark size of every degree): rows sampled across
+    the domain, including the first and last rows of every block, computed
+    one by one by the oracle."""
     torch = need_gpu()
     n = 64
     mg = StokesMG(n, k, n_levels=1)

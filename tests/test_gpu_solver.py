@@ -3,6 +3,9 @@ inverse, smoothing), the manufactured right-hand side, and FGMRES against the
 oracle (tight local CG, so the local solves equal the oracle's pseudo-
 inverse).  Then the full solve: FP64 and FP32 V-cycle reach 1e-8, pressures
 with zero mean, L2 errors equal to the oracle's direct solution."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -14,6 +17,7 @@ from paper_2410_09497_amd import StokesMG
 from paper_2410_09497_amd.synth import uniform_vector
 
 pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.mark.parametrize("n,k", [(2, 1), (4, 1), (4, 2), (8, 1), (4, 3)])
@@ -26,6 +30,22 @@ def test_vcycle_f64(n, k):
     xref = mg_o.vcycle(b)
     announce("vcycle f64", f"n={n} k={k}")
     mg = StokesMG(n, k, cg_rtol=1e-14, cg_max_it=500)
+    x = mg.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
+    assert rel_err(x, xref) <= 1e-10
+
+
+def test_vcycle_f64_degree4():
+    """The V-cycle at degree 4 (levels 1^3, 2^3, 4^3) against the oracle's,
+    whose patch pseudo-inverses go through the bordered sparse LU."""
+    torch = need_gpu()
+    n, k = 4, 4
+    mg_o = Multigrid(n, k, local_solver="bordered")
+    S = mg_o.fine["S"]
+    b = uniform_vector(S.ndof, seed=48)
+    b[S.offsets[3]:] -= b[S.offsets[3]:].mean()
+    xref = mg_o.vcycle(b)
+    announce("vcycle f64", f"n={n} k={k}")
+    mg = StokesMG(n, k, cg_rtol=1e-14, cg_max_it=1000)
     x = mg.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
     assert rel_err(x, xref) <= 1e-10
 
@@ -132,15 +152,68 @@ def test_solve_f32_vcycle_reaches_tolerance(k):
     assert abs(eu - eu_d) <= 1e-3 * eu_d and abs(ep - ep_d) <= 1e-3 * ep_d
 
 
+@pytest.mark.xfail(strict=False, reason=(
+    "measured with the readings built here (restriction P^T, ascending colours, penalty 2(k+1)^2/h, "
+    "exact local solves), sine problem on 8^3 cells, k = 3: steps end at 4.7e-4, 1.7e-6, 1.10e-8, "
+    "1.1e-10 -- the third step misses 1e-8 by 10 %; reversed post-smoothing colours and the "
+    "paper's own phi-based right-hand side (mu = 0.5 or 0.3, sigma = 0.1 .. 0.25) need 4 or 5 "
+    "steps too; a penalty of 4(k+1)^2/h would give three"))
 def test_solve_paper_three_steps_k3():
-    """Sec. 3.3 reports at most three GMRES steps to 1e-8 from k = 3.  With
-    the readings built here (restriction P^T, ascending colours, the sine
-    problem on 8^3 cells) the third step ends at 1.1e-8, just above 1e-8, and
-    the fourth reaches 1e-10: the band checked is three steps to 2e-8."""
+    """Sec. 3.3: from k = 3 on, at most three GMRES steps to 1e-8 in 3D."""
     torch = need_gpu()
+    gold = json.load(open(os.path.join(GOLDEN, "paper_iterations.json")))["three_d_max_steps_from_k3"]
     announce("three steps k=3")
-    mg = StokesMG(8, 3, cg_rtol=1e-10, cg_max_it=200)
+    mg = StokesMG(8, gold["k_min"], cg_rtol=1e-10, cg_max_it=200)
     b = mg.rhs_manufactured()
-    x, info = mg.solve(b, rtol=1e-8)
-    assert info["converged"] and info["iterations"] <= 4, info["history"]
-    assert info["history"][3] <= 2e-8, info["history"]
+    x, info = mg.solve(b, rtol=gold["rtol"])
+    assert info["converged"], info["history"]
+    assert info["iterations"] <= gold["max_steps"], info["history"]
+
+
+@pytest.mark.xfail(strict=False, reason=(
+    "measured: RT_2 on 32^3 cells (sine problem, exact local solves) needs 4 FGMRES steps to 1e-6 "
+    "(the third ends at about 3e-6); the paper's right-hand side parameters are not recoverable"))
+def test_table_vs_poisson_rt2_iterations():
+    """Table vs_poisson (Sec. 4.4), Stokes RT_2 column: 32^3 cells, three
+    iterations to a relative residual of 1e-6."""
+    torch = need_gpu()
+    gold = json.load(open(os.path.join(GOLDEN, "paper_iterations.json")))["table_vs_poisson_stokes"]["RT2"]
+    announce("table vs_poisson RT2", f"n={gold['n']}")
+    mg = StokesMG(gold["n"], gold["k"], cg_rtol=1e-10, cg_max_it=200)
+    b = mg.rhs_manufactured()
+    x, info = mg.solve(b, rtol=gold["rtol"], max_it=20, allow_notconv=True)
+    print("history", info["history"], flush=True)
+    assert info["converged"], info["history"]
+    assert info["iterations"] <= gold["iterations"], info["history"]
+
+
+def test_mixed_solve_16_matches_oracle():
+    """The mixed-precision solve at the oracle-comparison size of the
+    128^3 configuration: 16^3 cells, k = 2 (435,456 unknowns), FP32 V-cycle in
+    FP64 FGMRES(30).  Against the oracle's solution of the same problem
+    (tests/golden/mixed16_k2_oracle.json, FGMRES + exact V-cycle to 1e-12):
+    at 1e-8 the L2 errors agree to 0.1 %; continued to 1e-11, the solution
+    agrees to 1e-7 relative at 2000 sampled indices."""
+    torch = need_gpu()
+    ref = json.load(open(os.path.join(GOLDEN, "mixed16_k2_oracle.json")))
+    n, k = ref["n"], ref["k"]
+    announce("mixed solve vs oracle", f"n={n} k={k}")
+    mg = StokesMG(n, k, cg_rtol=1e-6, cg_max_it=100)
+    assert mg.ndof() == ref["ndof"]
+    b = mg.rhs_manufactured()
+    x, info = mg.solve(b, rtol=1e-8, vcycle_dtype="f32")
+    assert info["converged"] and info["rel_residual"] <= 1e-8
+    S = Stokes(n, k)
+    xh = x.cpu().numpy()
+    eu, ep = S.l2_errors(xh, mf.sine_u, mf.sine_p)
+    assert abs(eu - ref["l2_error_u"]) <= 1e-3 * ref["l2_error_u"]
+    assert abs(ep - ref["l2_error_p"]) <= 1e-3 * ref["l2_error_p"]
+    assert abs(S.pressure_mean(xh)) <= 1e-12 * ref["max_abs"]
+    idx = np.array(ref["indices"])
+    vals = np.array(ref["values"])
+    d8 = np.abs(xh[idx] - vals).max() / ref["max_abs"]
+    x, info = mg.solve(b, rtol=1e-11, vcycle_dtype="f32", max_it=60)
+    assert info["converged"]
+    d11 = np.abs(x.cpu().numpy()[idx] - vals).max() / ref["max_abs"]
+    print(f"max sampled difference / max|x|: {d8:.2e} at 1e-8, {d11:.2e} at 1e-11", flush=True)
+    assert d11 <= 1e-7

@@ -120,3 +120,41 @@ def test_patch_pressure_kernel():
     assert np.abs(Kj @ z).max() < 1e-13
     lam = np.linalg.eigvalsh(Kj)
     assert (np.abs(lam) < 1e-10 * np.abs(lam).max()).sum() == 1
+
+
+@pytest.mark.parametrize("n,k", [(3, 1), (4, 2), (3, 3)])
+def test_bordered_route_equals_pseudo_inverse(n, k):
+    """The bordered sparse-LU route to K_j^+ r (used for degrees 4, 5) equals
+    the dense pseudo-inverse on every patch type, also for a right-hand side
+    whose patch pressure part has nonzero mean.  Both are exact up to
+    rounding: at k = 3 the eigendecomposition route leaves a relative
+    residual ||K_j x - r'|| of about 5e-11 (the bordered LU 2e-12), which the
+    saddle-point system turns into differences of about 1e-10 relative, so
+    the bound is 1e-9."""
+    S = Stokes(n, k)
+    K = S.assemble()
+    Pd, Pb = Patches(S), Patches(S, solver="bordered")
+    rng = np.random.default_rng(5)
+    for v in Pd.verts:
+        r = rng.uniform(-1, 1, Pd.size)
+        a = Pd.local_solve(K, v, r)
+        b = Pb.local_solve(K, v, r)
+        assert np.abs(a - b).max() <= 1e-9 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_bordered_route_solves_large_patches(k):
+    """Degrees 4, 5 (one patch on 2^3 cells): K_j x = r - mean-part and
+    x has zero patch-pressure mean, i.e. x = K_j^+ r."""
+    S = Stokes(2, k)
+    K = S.assemble()
+    P = Patches(S, solver="bordered")
+    v = P.verts[0]
+    Kj = P.local_matrix(K, v)
+    r = np.random.default_rng(k).uniform(-1, 1, P.size)
+    x = P.local_solve(K, v, r)
+    c = np.zeros(P.size)
+    c[3 * P.nvel:] = 1.0
+    rp = r - (c @ r) / (c @ c) * c
+    assert abs(c @ x) <= 1e-10 * np.abs(x).max()
+    assert np.abs(Kj @ x - rp).max() <= 1e-9 * np.abs(rp).max()
