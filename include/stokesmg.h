@@ -128,6 +128,26 @@ int stokes_residual(stokesmg_t* h, int level, int dtype, const void* b, const vo
  * Degrees 1..5. */
 int patch_smooth(stokesmg_t* h, int level, int dtype, void* x, const void* b, int n_sweeps, void* stream);
 
+/* For callers that cannot allocate device memory at the call site (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): patch_smooth with the same arguments and the same kernels, whose
+ * per-call scratch -- the residual vector of the colour loop and the two CG
+ * counters -- lives in a static device array of the library
+ * (STOKESMG_NOALLOC_SCRATCH_BYTES per device, held until the process ends)
+ * instead of the workspace.  The level tables still come from the workspace
+ * set at setup (ENOMEM without one).  The call allocates nothing.
+ * Limit: 256 + (level unknowns) x (8 for F64, 4 for F32) bytes must fit the
+ * array (32 MiB: e.g. 32^3 cells at k = 2 in F64), else EINVAL.
+ * cg_iterations (host pointer, may be NULL): if given, the total local CG
+ * iterations of this call; the call then synchronizes `stream`.
+ * All calls on one device share its array and keep the last call's contents:
+ * calls that overlap in time on one device (two streams, two threads) race. */
+#define STOKESMG_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int patch_smooth_noalloc(stokesmg_t* h, int level, int dtype, void* x, const void* b, int n_sweeps,
+                         int64_t* cg_iterations, void* stream);
+/* *bytes = STOKESMG_NOALLOC_SCRATCH_BYTES (no device needed). */
+int stokesmg_noalloc_scratch_size(size_t* bytes);
+
 /* Total local CG iterations and local solves performed by patch_smooth since
  * the last reset (reset = 1 zeroes them after reading).  Synchronizes
  * `stream`. */

@@ -129,6 +129,20 @@ class StokesMG:
                                           self._stream()))
         return x
 
+    def smooth_noalloc(self, x, b, level=-1, sweeps=1):
+        """patch_smooth_noalloc: the same sweeps with the library's static
+        device scratch instead of the workspace; returns the local CG
+        iterations of the call (synchronizes the stream)."""
+        level = level % self.n_levels
+        self._vec(x, level, "x")
+        self._vec(b, level, "b")
+        if x.dtype != b.dtype:
+            raise TypeError("x and b must share a dtype")
+        it = ctypes.c_int64(-1)
+        self._check(_lib.lib.patch_smooth_noalloc(self._h, level, self._dtype_code(x), x.data_ptr(), b.data_ptr(),
+                                                  sweeps, ctypes.byref(it), self._stream()))
+        return it.value
+
     def cg_stats(self, reset=True):
         """(local CG iterations, local solves) since the last reset."""
         a, b = ctypes.c_int64(), ctypes.c_int64()

@@ -51,6 +51,8 @@ def _load():
         "stokes_residual": (i32, [vp, i32, i32, vp, vp, vp, vp]),
         "patch_smooth": (i32, [vp, i32, i32, vp, vp, i32, vp]),
         "stokesmg_cg_stats": (i32, [vp, i64p, i64p, i32, vp]),
+        "patch_smooth_noalloc": (i32, [vp, i32, i32, vp, vp, i32, i64p, vp]),
+        "stokesmg_noalloc_scratch_size": (i32, [szp]),
         "vcycle": (i32, [vp, i32, vp, vp, vp]),
         "stokesmg_solve_workspace_size": (i32, [vp, i32, i32, szp]),
         "solve": (i32, [vp, vp, vp, ctypes.c_double, i32, i32, i32, vp, ctypes.c_size_t, ctypes.POINTER(Info), vp]),
