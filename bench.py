@@ -12,12 +12,14 @@ operator on a bounded sample of the same problem family on this host.
 Inputs rotate over enough (x, y) pairs that the working set exceeds the
 256 MB Infinity Cache, so the figure is an HBM figure.
 
-Second part of the metric, `solve`: time to a relative residual of 1e-8 of
-FGMRES(30) preconditioned by the V-cycle on 128^3 cells, RT_2 (226 M
-unknowns, 8 levels), for the manufactured sine problem: all-FP64 multigrid,
-FP32 V-cycle (mixed precision), and FP32 V-cycle with the learned local
-solver (trained first on ~10^6 pairs captured from exact V-cycles on 32^3
-cells with random smooth right-hand sides) with the exact-solver fallback.
+Second part of the metric, `solve` (k = 2) and `solve_k3` (k = 3): time to
+a relative residual of 1e-8 of FGMRES(8) preconditioned by the V-cycle on
+128^3 cells (226 M / 536 M unknowns, 8 levels): all-FP64 multigrid, the FP32
+V-cycle, the FP32 V-cycle with the Direct local solver on the matrix cores,
+and -- on random smooth right-hand sides from an unseen seed -- the learned
+local solver with its exact-solver fallback and the network's pressure as
+the start of the exact local CG (network trained first on pairs captured
+from exact V-cycles on 32^3 cells).
 
 Third part, `c1`: the operator and the smoother for every degree k = 1..5 in
 FP64 and FP32 at 64^3 cells (K applications and a few sweeps per cell).
@@ -149,47 +151,47 @@ def c1_section(dev, n, steps, sweeps, log):
     return out
 
 
-def solve_section(dev, k, n_solve, log):
-    """FP64 MG vs FP32 MG vs learned MG: time to 1e-8 (wall time of solve())."""
-    import numpy as np
+def _run(mg, b, log, name, solver="exact", mode="bf16", vcycle="f32", rho_ref=0.0):
+    mg.set_local_solver(solver, mode)
+    if solver == "mlp":
+        mg.set_fallback(rho_ref)
+    x, info = mg.solve(b, rtol=1e-8, max_it=30, vcycle_dtype=vcycle, restart=8, allow_notconv=True)
+    mg.set_local_solver("exact")
+    out = {"seconds": info["seconds"], "iterations": info["iterations"], "rel_residual": info["rel_residual"],
+           "converged": info["converged"], "nu": info["nu"], "history": info["history"],
+           "avg_local_cg": info["cg_iterations"] / max(info["local_solves"], 1),
+           "local_solver": solver, "vcycle": vcycle, "operands": mode if solver != "exact" else None}
+    if solver == "mlp":
+        fb = info["fallback_iteration"]
+        out.update(fallback_iteration=fb, rho_ref=rho_ref, fallback_bound=max(2 * rho_ref, 1e-3),
+                   learned_steps_used=info["iterations"] if fb < 0 else fb)
+    log(f"[bench] {name}: {info['seconds']:.3f} s, {info['iterations']} steps, "
+        f"avg local CG {out['avg_local_cg']:.2f}")
+    return out
+
+
+def train_network(dev, k, pairs, epochs, log):
+    """Pairs (normalized patch residual, exact correction) from exact FP64
+    V-cycles on 32^3 cells with random smooth right-hand sides (seeds 0, 1,
+    ...), then Adam on the BF16 MFMA kernels."""
     import torch
     from paper_2410_09497_amd import StokesMG
-
-    out = {"workload": f"FGMRES(30) + V(1,1) to 1e-8 on {n_solve}^3 cells, RT_{k}/DG Q_{k}, manufactured sine "
-                       "problem, levels down to 1^3; local Schur CG rtol 1e-3, at most 15 iterations"}
-    mg = StokesMG(n_solve, k, cg_rtol=1e-3, cg_max_it=15, device=dev)
-    out["unknowns"] = mg.ndof()
-    b = mg.rhs_manufactured()
-    runs = {}
-    for name, vd in (("fp64_mg", "f64"), ("fp32_mg", "f32")):
-        x, info = mg.solve(b, rtol=1e-8, max_it=60, vcycle_dtype=vd, allow_notconv=True)
-        runs[name] = {"seconds": info["seconds"], "iterations": info["iterations"],
-                      "rel_residual": info["rel_residual"], "nu": info["nu"],
-                      "history": info["history"],
-                      "avg_local_cg": info["cg_iterations"] / max(info["local_solves"], 1)}
-        log(f"[bench] {name}: {info['seconds']:.3f} s, {info['iterations']} iterations")
-    h = runs["fp32_mg"]["history"]
-    rho_ref = h[-1] ** (1.0 / max(runs["fp32_mg"]["iterations"], 1))
-
-    # learned local solver: pairs from exact FP64 V-cycles on 32^3 cells, training, then the solve
     nt = 32
     tr = StokesMG(nt, k, cg_rtol=1e-10, cg_max_it=200, device=dev)
     tr.mlp_setup(65536)
     tr.mlp_init(seed=0)
     d, _ = tr.mlp_dims()
-    cap = 1_000_000
-    X = torch.empty(cap, d, dtype=torch.float32, device=dev)
+    X = torch.empty(pairs, d, dtype=torch.float32, device=dev)
     T = torch.empty_like(X)
     cnt, s = 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    while cnt < cap:
-        f = tr.rhs_fourier(seed=s)
-        cnt, _ = tr.mlp_collect_pairs(f, X, T, n=cnt)
+    while cnt < pairs:
+        cnt, _ = tr.mlp_collect_pairs(tr.rhs_fourier(seed=s), X, T, n=cnt)
         s += 1
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0
-    epochs, batch = 20, 4096
+    batch = 4096
     t0 = time.perf_counter()
     hist = tr.mlp_train(X, T, n=cnt, epochs=epochs, batch=batch, lr=1e-3, seed=1)
     torch.cuda.synchronize()
@@ -199,38 +201,70 @@ def solve_section(dev, k, n_solve, log):
     state, step = tr.mlp_get_state()
     del tr, X, T
     torch.cuda.empty_cache()
-    out["training"] = {"pairs": cnt, "v_cycles": s, "collect_seconds": t_collect, "epochs": epochs, "batch": batch,
-                       "train_seconds": t_train, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
-                       "samples_per_s": epochs * cnt / t_train,
-                       "tflops": epochs * cnt * flop_per_sample / t_train / 1e12,
-                       "mfma_peak_tflops_bf16": 2500.0,
-                       "workload": f"pairs from exact FP64 V-cycles on {nt}^3 cells, RT_{k}, random smooth "
-                                   "right-hand sides (8 Fourier modes per component, wavenumbers 1..8); "
-                                   f"MLP {d}-256-256-{d}, GELU, BF16 operands, FP32 accumulation, Adam"}
-    log(f"[bench] training: {cnt} pairs, {t_train:.2f} s for {epochs} epochs")
-    mg.mlp_setup(65536)
+    log(f"[bench] training k={k}: {cnt} pairs, {t_train:.2f} s for {epochs} epochs")
+    info = {"pairs": cnt, "v_cycles": s, "collect_seconds": t_collect, "epochs": epochs, "batch": batch,
+            "train_seconds": t_train, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+            "samples_per_s": epochs * cnt / t_train, "tflops": epochs * cnt * flop_per_sample / t_train / 1e12,
+            "mfma_peak_tflops_bf16": 2500.0,
+            "workload": f"pairs from exact FP64 V-cycles on {nt}^3 cells, RT_{k}, random smooth right-hand sides "
+                        f"(8 Fourier modes per component, wavenumbers 1..8, seeds 0..{s - 1}); MLP {d}-256-256-{d}, "
+                        "GELU, BF16 operands, FP32 accumulation, Adam"}
+    return state, step, info
+
+
+def solve_section(dev, k, n_solve, log):
+    """Time to 1e-8 (wall time of solve()) of FGMRES(8) with the V-cycle on
+    n_solve^3 cells.  The manufactured sine problem: all-FP64 multigrid, the
+    FP32 V-cycle, and the FP32 V-cycle whose interior local solves are the
+    Direct solver on the matrix cores (BF16 and FP32 operands).  Random smooth
+    right-hand sides from an unseen seed: the same, plus the learned local
+    solver (the network in place of the interior local solves, with the
+    exact-solver fallback) and the network's pressure as the start of the
+    exact Schur CG."""
+    import torch
+    from paper_2410_09497_amd import StokesMG
+
+    mg = StokesMG(n_solve, k, cg_rtol=1e-3, cg_max_it=15, device=dev)
+    mg.mlp_setup(131072)
+    t0 = time.perf_counter()
+    mg.direct_setup()
+    t_direct = time.perf_counter() - t0
+    out = {"workload": f"FGMRES(8) + V(1,1) to 1e-8 on {n_solve}^3 cells, RT_{k}/DG Q_{k}, levels down to 1^3; "
+                       "local Schur CG rtol 1e-3, at most 15 iterations",
+           "unknowns": mg.ndof(), "direct_setup_seconds": t_direct}
+    b = mg.rhs_manufactured()
+    sine = {"problem": "manufactured sine problem"}
+    sine["fp64_mg"] = _run(mg, b, log, "sine fp64_mg", vcycle="f64")
+    sine["fp32_mg"] = _run(mg, b, log, "sine fp32_mg")
+    sine["fp32_direct_bf16"] = _run(mg, b, log, "sine fp32_direct_bf16", "direct", "bf16")
+    sine["fp32_direct_f32"] = _run(mg, b, log, "sine fp32_direct_f32", "direct", "f32")
+    for v in ("fp32_mg", "fp32_direct_bf16", "fp32_direct_f32"):
+        sine[v + "_speedup_vs_fp64"] = sine["fp64_mg"]["seconds"] / sine[v]["seconds"]
+    out["sine"] = sine
+    h = sine["fp32_mg"]["history"]
+    rho_ref = h[-1] ** (1.0 / max(sine["fp32_mg"]["iterations"], 1))
+
+    state, step, tinfo = train_network(dev, k, 1_000_000 if k == 2 else 400_000, 20 if k == 2 else 10, log)
+    out["training"] = tinfo
     mg.mlp_set_state(state, step)
-    mg.set_local_solver("mlp", "bf16")
-    mg.set_fallback(rho_ref)
-    x, info = mg.solve(b, rtol=1e-8, max_it=60, vcycle_dtype="f32", allow_notconv=True)
-    mg.set_local_solver("exact")
-    fb = info["fallback_iteration"]
-    runs["learned_mg"] = {"seconds": info["seconds"], "iterations": info["iterations"],
-                          "rel_residual": info["rel_residual"], "history": info["history"],
-                          "fallback_iteration": fb, "rho_ref": rho_ref,
-                          "fallback_bound": max(2 * rho_ref, 1e-3),
-                          "learned_contraction": (info["history"][1] if fb != 0 and len(info["history"]) > 1
-                                                  else None)}
-    log(f"[bench] learned_mg: {info['seconds']:.3f} s, {info['iterations']} iterations, fallback after {fb}")
-    out.update(runs)
-    out["fp32_speedup_vs_fp64"] = runs["fp64_mg"]["seconds"] / runs["fp32_mg"]["seconds"]
-    # a learned speed-up exists only when every step used the network (the fallback never fired)
-    runs["learned_mg"]["learned_steps_used"] = info["iterations"] if fb < 0 else fb
-    out["learned_speedup_vs_fp64"] = (runs["fp64_mg"]["seconds"] / runs["learned_mg"]["seconds"]
-                                      if fb < 0 else None)
+    seed = 1_000_000 + 7
+    bf = mg.rhs_fourier(seed=seed)
+    four = {"problem": f"random smooth right-hand side, unseen seed {seed}"}
+    four["fp64_mg"] = _run(mg, bf, log, "fourier fp64_mg", vcycle="f64")
+    four["fp32_mg"] = _run(mg, bf, log, "fourier fp32_mg")
+    four["fp32_direct_bf16"] = _run(mg, bf, log, "fourier fp32_direct_bf16", "direct", "bf16")
+    four["fp32_mlp"] = _run(mg, bf, log, "fourier fp32_mlp", "mlp", "bf16", rho_ref=rho_ref)
+    four["fp32_mlp_warm"] = _run(mg, bf, log, "fourier fp32_mlp_warm", "mlp_warm", "bf16")
+    for v in ("fp32_mg", "fp32_direct_bf16", "fp32_mlp", "fp32_mlp_warm"):
+        four[v + "_speedup_vs_fp64"] = four["fp64_mg"]["seconds"] / four[v]["seconds"]
+    fb = four["fp32_mlp"]["fallback_iteration"]
     if fb >= 0:
-        out["learned_note"] = (f"the contraction monitor handed the solve to the exact local solver after "
-                               f"{fb} learned step(s); the learned variant gains nothing on this problem")
+        four["learned_note"] = (f"the network in place of the local solve: the contraction monitor handed the solve "
+                                f"to the exact local solver after {fb} learned step(s)")
+    four["warm_note"] = (f"the network's pressure as the start of the exact Schur CG: "
+                         f"{four['fp32_mlp_warm']['avg_local_cg']:.2f} local CG iterations per patch against "
+                         f"{four['fp32_mg']['avg_local_cg']:.2f} without it, same stopping test")
+    out["fourier"] = four
     del mg
     torch.cuda.empty_cache()
     return out
@@ -249,6 +283,7 @@ def main():
     ap.add_argument("--solve-n", type=int, default=128)
     ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--c1-sweeps", type=int, default=3)
+    ap.add_argument("--no-k3", action="store_true", help="skip the degree-3 solves (C4 at k = 3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the method's hot path here is single-GPU "
@@ -339,6 +374,8 @@ def main():
         out["c1"] = c1_section(dev, args.n, args.steps, args.c1_sweeps, log)
     if not args.no_solve:
         out["solve"] = solve_section(dev, k, args.solve_n, log)
+        if not args.no_k3 and k != 3:
+            out["solve_k3"] = solve_section(dev, 3, args.solve_n, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(k)
     print(json.dumps(out))

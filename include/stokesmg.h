@@ -245,6 +245,16 @@ int stokesmg_rhs_fourier(stokesmg_t* h, int level, int n_modes, const int* kappa
 #define STOKESMG_LOCAL_MLP   1   /* network on interior patches, exact solve on the others; the
                                     learned patch pressure is projected to zero coefficient mean,
                                     as the exact correction (orthogonal to the kernel of K_j) is */
+#define STOKESMG_LOCAL_MLP_WARM 2 /* exact solve everywhere; on interior patches the Schur CG starts
+                                    from the pressure the network predicts instead of zero, with the
+                                    same stopping test (relative to the cold-start residual): the
+                                    exact solver judges, the network only saves iterations */
+#define STOKESMG_LOCAL_DIRECT 3  /* the "Direct" solver of Sec. 3.3 on interior patches: the patch
+                                    pseudo-inverse as one dense matrix (the same on every level in
+                                    the normalized variables of the gather), applied to a colour's
+                                    interior patches as one GEMM on the matrix cores (BF16 or FP32
+                                    operands per mlp_mode, FP32 accumulation); the Schur CG on the
+                                    boundary patches.  Needs stokesmg_direct_setup(). */
 
 /* d (network width in and out) and P (parameter count) for the handle's degree. */
 int mlp_dims(const stokesmg_t* h, int64_t* d, int64_t* n_params);
@@ -294,9 +304,22 @@ int mlp_train(stokesmg_t* h, int mode, const float* X, const float* T, int64_t n
 
 /* Local solver used by patch_smooth, vcycle and solve from now on, the
  * network's precision, and a damping factor in (0, 1] applied to the learned
- * corrections (1 = undamped).  STOKESMG_LOCAL_MLP needs an MLP workspace
- * with parameters. */
+ * corrections (1 = undamped; unused by STOKESMG_LOCAL_MLP_WARM and
+ * STOKESMG_LOCAL_DIRECT).  The two learned solvers need an MLP workspace with
+ * parameters; the Direct solver needs stokesmg_direct_setup(). */
 int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode, double mlp_damping);
+
+/* The Direct solver's matrix (Sec. 3.3 "Direct solver", interior patches):
+ * t = M x with x = (F / h, G / h^2) and t = (U, h P) for the patch residual
+ * (F, G) and its exact correction (U, P) = K_j^+ (F, G); the same on every
+ * level.  Built on the host in FP64 from the fast-diagonalization tables via
+ * the Schur complement of Sec. 3.2 and checked between two levels.
+ * stokesmg_direct_matrix writes it to host memory (d x d doubles, row-major
+ * [out][in], d from mlp_dims; no device needed).  stokesmg_direct_setup
+ * uploads it (FP32) into the MLP workspace, which must be set (ENOMEM) and
+ * has room for it; synchronizes `stream`.  Degrees 1..3 (EUNSUPPORTED). */
+int stokesmg_direct_matrix(const stokesmg_t* h, double* M);
+int stokesmg_direct_setup(stokesmg_t* h, void* stream);
 
 /* Fallback of the learned solver inside solve(): with the MLP local solver,
  * after FGMRES step j with contraction rho_j = res_j / res_{j-1} of the

@@ -305,8 +305,20 @@ class StokesMG:
         return [hist[i] for i in range(epochs)]
 
     def set_local_solver(self, solver="exact", mode="bf16", damping=1.0):
-        self._check(_lib.lib.stokesmg_set_local_solver(self._h, {"exact": 0, "mlp": 1}[solver], self._mode(mode),
+        self._check(_lib.lib.stokesmg_set_local_solver(self._h, {"exact": 0, "mlp": 1, "mlp_warm": 2, "direct": 3}[solver], self._mode(mode),
                                                        float(damping)))
+
+    def direct_matrix(self):
+        """The Direct solver's normalized interior map (host, FP64, [out][in])."""
+        import numpy as np
+        d, _ = self.mlp_dims()
+        M = np.empty((d, d), dtype=np.float64)
+        self._check(_lib.lib.stokesmg_direct_matrix(self._h, M.ctypes.data))
+        return M
+
+    def direct_setup(self):
+        """Uploads the Direct solver's matrix into the MLP workspace (mlp_setup first)."""
+        self._check(_lib.lib.stokesmg_direct_setup(self._h, self._stream()))
 
     def set_fallback(self, rho_ref):
         self._check(_lib.lib.stokesmg_set_fallback(self._h, float(rho_ref)))

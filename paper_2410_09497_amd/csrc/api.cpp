@@ -77,7 +77,7 @@ int stokesmg_create(const stokesmg_config* cfg, stokesmg_t** out) {
         off = align256(off + psz * sizeof(float));
     }
     h->cg_counter = off;
-    off = align256(off + 2 * sizeof(int));
+    off = align256(off + 2 * sizeof(unsigned long long));
     h->r_vec = off;
     off = align256(off + size_t(level_total(h, L - 1)) * sizeof(double));
     h->c_vec = off;
@@ -178,7 +178,7 @@ int stokesmg_set_workspace(stokesmg_t* h, void* dev_ptr, size_t bytes, void* str
                                   hipMemcpyHostToDevice, st));
         SMG_HIP(h, hipStreamSynchronize(st));
     }
-    SMG_HIP(h, hipMemsetAsync(h->ws + h->cg_counter, 0, 2 * sizeof(int), st));
+    SMG_HIP(h, hipMemsetAsync(h->ws + h->cg_counter, 0, 2 * sizeof(unsigned long long), st));
     SMG_HIP(h, hipStreamSynchronize(st));
     return STOKESMG_OK;
 }
@@ -231,13 +231,13 @@ int stokesmg_cg_stats(stokesmg_t* h, int64_t* iterations, int64_t* solves, int r
     if (!h) return STOKESMG_EINVAL;
     if (!h->ws) return h->fail(STOKESMG_ENOMEM, "no workspace set");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int c[2] = {0, 0};
+    unsigned long long c[2] = {0, 0};
     SMG_HIP(h, hipMemcpyAsync(c, h->ws + h->cg_counter, sizeof(c), hipMemcpyDeviceToHost, st));
     SMG_HIP(h, hipStreamSynchronize(st));
-    if (iterations) *iterations = c[0];
-    if (solves) *solves = c[1];
+    if (iterations) *iterations = int64_t(c[0]);
+    if (solves) *solves = int64_t(c[1]);
     if (reset) {
-        SMG_HIP(h, hipMemsetAsync(h->ws + h->cg_counter, 0, 2 * sizeof(int), st));
+        SMG_HIP(h, hipMemsetAsync(h->ws + h->cg_counter, 0, 2 * sizeof(unsigned long long), st));
         SMG_HIP(h, hipStreamSynchronize(st));
     }
     return STOKESMG_OK;

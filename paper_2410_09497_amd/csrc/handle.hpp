@@ -25,7 +25,7 @@ struct stokesmg {
     std::vector<size_t> ptab_f64, ptab_f32;  // per level (patch tables; unused for n < 2)
     size_t r_vec = 0;                        // residual vector of the finest level (8 B per unknown)
     size_t c_vec = 0;                        // correction vector of the finest level (pair capture)
-    size_t cg_counter = 0;                   // two int counters: CG iterations, patch solves
+    size_t cg_counter = 0;                   // two 64-bit counters: CG iterations, patch solves
     size_t ws_needed = 0;
 
     // multigrid: transfers between level l-1 and l (index l >= 1), coarse pseudo-inverse,
@@ -54,6 +54,8 @@ struct stokesmg {
         int d = 0, H = 256;
         int64_t P = 0;             // parameter count
         size_t params, grads, m, v, Z1, H1, Z2, H2, Y, dY, dZ2, dZ1, X, s, split, lossp, loss, colp, brows, acc;
+        size_t direct = 0;         // the Direct solver's normalized interior map, d x d FP32 [in][out]
+        bool direct_ready = false; // stokesmg_direct_setup() has filled it
         size_t split_floats = 0;
         int64_t step = 0;          // Adam steps taken
         bool ready = false;        // parameters initialized or set

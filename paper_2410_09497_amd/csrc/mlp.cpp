@@ -13,6 +13,7 @@
 #include "mlp.hpp"
 #include "mlp_kernels.hpp"
 #include "patch.hpp"
+#include "direct.hpp"
 
 namespace {
 
@@ -55,6 +56,7 @@ size_t layout(stokesmg::Mlp& m, int d, int H, int64_t R) {
     put(m.colp, size_t(smg::kColsumSplit) * (d > H ? d : H) * f);
     put(m.brows, R * sizeof(int));
     put(m.acc, sizeof(double));
+    put(m.direct, size_t(d) * d * f);
     return off;
 }
 
@@ -179,14 +181,55 @@ int mlp_interior_solve(stokesmg* h, int level, bool f64, void* x, const void* r,
     return STOKESMG_OK;
 }
 
+// interior patches of one colour by the Direct solver: gather, one GEMM with the normalized map on the
+// matrix cores (BF16 or FP32 operands per the MLP mode, FP32 accumulation), scatter
+int direct_interior_solve(stokesmg* h, int level, bool f64, void* x, const void* r, int colour, hipStream_t st) {
+    auto& m = h->mlp;
+    const int n = h->lv[level].n, k = h->cfg.k;
+    const int64_t np = interior_count(n, colour);
+    const bool bf16 = h->mlp_mode == STOKESMG_MLP_BF16;
+    float *X = at<float>(h, m.X), *Y = at<float>(h, m.Y), *s = at<float>(h, m.s);
+    const float* Mt = at<float>(h, m.direct);
+    for (int64_t p0 = 0; p0 < np; p0 += m.rows) {
+        const int cnt = int(std::min<int64_t>(m.rows, np - p0));
+        SMG_HIP(h, launch_patch_gather(f64, r, n, k, colour, int(p0), cnt, X, m.d, s, st));
+        SMG_HIP(h, launch_gemm(bf16, Epi::Store, false, false, cnt, m.d, m.d, X, m.d, nullptr, Mt, m.d, Y, m.d,
+                               nullptr, nullptr, 0, nullptr, 0, st));
+        SMG_HIP(h, launch_patch_scatter(f64, x, n, k, colour, int(p0), cnt, Y, m.d, s, 1.0, st));
+    }
+    return STOKESMG_OK;
+}
+
+// interior patches of one colour with the Schur CG started from the network's pressure
+int mlp_warm_solve(stokesmg* h, int level, bool f64, void* x, const void* r, const void* ptab, int colour,
+                   unsigned long long* counters, hipStream_t st) {
+    auto& m = h->mlp;
+    const int n = h->lv[level].n, k = h->cfg.k;
+    const int64_t np = interior_count(n, colour);
+    const bool bf16 = h->mlp_mode == STOKESMG_MLP_BF16;
+    float *X = at<float>(h, m.X), *Y = at<float>(h, m.Y), *s = at<float>(h, m.s);
+    for (int64_t p0 = 0; p0 < np; p0 += m.rows) {
+        const int cnt = int(std::min<int64_t>(m.rows, np - p0));
+        SMG_HIP(h, launch_patch_gather(f64, r, n, k, colour, int(p0), cnt, X, m.d, s, st));
+        if (int rc = forward(h, bf16, X, nullptr, cnt, Y, false, st)) return rc;
+        SMG_HIP(h, launch_patch_solve_warm(k, f64, x, r, ptab, n, colour, h->cfg.cg_rtol, h->cfg.cg_max_it, counters,
+                                           int(p0), cnt, Y, m.d, s, st));
+    }
+    return STOKESMG_OK;
+}
+
 int smooth_sweep(stokesmg* h, int level, bool f64, void* x, const void* b, hipStream_t st, const Capture* cap,
-                 void* r_in, int* counters_in, bool own_counters) {
+                 void* r_in, unsigned long long* counters_in, bool own_counters) {
     const int n = h->lv[level].n, k = h->cfg.k;
     const void* tab = h->ws + (f64 ? h->tab_f64[level] : h->tab_f32[level]);
     const void* ptab = h->ws + (f64 ? h->ptab_f64[level] : h->ptab_f32[level]);
     void* r = r_in ? r_in : h->ws + h->r_vec;
-    int* counters = own_counters ? counters_in : reinterpret_cast<int*>(h->ws + h->cg_counter);
+    unsigned long long* counters = own_counters ? counters_in : reinterpret_cast<unsigned long long*>(h->ws + h->cg_counter);
     const bool learned = h->local_solver == STOKESMG_LOCAL_MLP && !cap;
+    const bool warm = h->local_solver == STOKESMG_LOCAL_MLP_WARM && !cap;
+    const bool direct = h->local_solver == STOKESMG_LOCAL_DIRECT && !cap;
+    if (direct && !h->mlp.direct_ready)
+        return h->fail(STOKESMG_EINVAL, "the Direct solver needs stokesmg_direct_setup() after mlp_set_workspace()");
     const size_t N = size_t(level_total(h, level));
     for (int c = 0; c < 8; ++c) {
         SMG_HIP(h, launch_apply(k, f64, true, x, b, r, tab, n, st));
@@ -213,6 +256,14 @@ int smooth_sweep(stokesmg* h, int level, bool f64, void* x, const void* b, hipSt
             SMG_HIP(h, launch_patch_solve(k, f64, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters,
                                           true, st));
             if (int rc = mlp_interior_solve(h, level, f64, x, r, c, st)) return rc;
+        } else if (direct && interior_count(n, c) > 0) {
+            SMG_HIP(h, launch_patch_solve(k, f64, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters,
+                                          true, st));
+            if (int rc = direct_interior_solve(h, level, f64, x, r, c, st)) return rc;
+        } else if (warm && interior_count(n, c) > 0) {
+            SMG_HIP(h, launch_patch_solve(k, f64, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters,
+                                          true, st));
+            if (int rc = mlp_warm_solve(h, level, f64, x, r, ptab, c, counters, st)) return rc;
         } else {
             SMG_HIP(h, launch_patch_solve(k, f64, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters,
                                           false, st));
@@ -399,14 +450,53 @@ int mlp_collect_pairs(stokesmg_t* h, const double* b, double* x, float* X, float
 int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode, double mlp_damping) {
     if (!h) return STOKESMG_EINVAL;
     if (!(mlp_damping > 0.0 && mlp_damping <= 1.0)) return h->fail(STOKESMG_EINVAL, "mlp_damping must be in (0, 1]");
-    if (local_solver != STOKESMG_LOCAL_EXACT && local_solver != STOKESMG_LOCAL_MLP)
+    if (local_solver != STOKESMG_LOCAL_EXACT && local_solver != STOKESMG_LOCAL_MLP &&
+        local_solver != STOKESMG_LOCAL_MLP_WARM && local_solver != STOKESMG_LOCAL_DIRECT)
         return h->fail(STOKESMG_EINVAL, "unknown local solver");
     if (int rc = check_mode(h, mlp_mode)) return rc;
-    if (local_solver == STOKESMG_LOCAL_MLP)
+    if (local_solver == STOKESMG_LOCAL_DIRECT) {
+        if (!h->mlp.ws || !h->mlp.direct_ready)
+            return h->fail(STOKESMG_EINVAL, "the Direct solver needs stokesmg_direct_setup() first");
+    } else if (local_solver != STOKESMG_LOCAL_EXACT) {
         if (int rc = check_mlp(h, true)) return rc;
+    }
     h->local_solver = local_solver;
     h->mlp_mode = mlp_mode;
     h->mlp_omega = mlp_damping;
+    return STOKESMG_OK;
+}
+
+int stokesmg_direct_matrix(const stokesmg_t* h, double* M) {
+    if (!h || !M) return STOKESMG_EINVAL;
+    if (h->cfg.k > 3) return STOKESMG_EUNSUPPORTED;
+    try {
+        const std::vector<double> D = smg::direct_interior_map(smg::Ref1D(h->cfg.k), h->cfg.penalty_factor);
+        std::memcpy(M, D.data(), D.size() * sizeof(double));
+    } catch (const std::exception&) {
+        return STOKESMG_EINVAL;
+    }
+    return STOKESMG_OK;
+}
+
+int stokesmg_direct_setup(stokesmg_t* h, void* stream) {
+    if (!h) return STOKESMG_EINVAL;
+    if (h->cfg.k > 3) return h->fail(STOKESMG_EUNSUPPORTED, "the Direct solver is built for degrees 1..3");
+    if (!h->mlp.ws) return h->fail(STOKESMG_ENOMEM, "no MLP workspace set (it holds the Direct solver's matrix)");
+    std::vector<double> D;
+    try {
+        D = smg::direct_interior_map(smg::Ref1D(h->cfg.k), h->cfg.penalty_factor);
+    } catch (const std::exception& e) {
+        return h->fail(STOKESMG_EINVAL, e.what());
+    }
+    const int d = h->mlp.d;
+    std::vector<float> Mt(size_t(d) * d);   // [in][out], the B operand of the GEMM
+    for (int o = 0; o < d; ++o)
+        for (int i = 0; i < d; ++i) Mt[size_t(i) * d + o] = float(D[size_t(o) * d + i]);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SMG_HIP(h, hipMemcpyAsync(h->mlp.ws + h->mlp.direct, Mt.data(), Mt.size() * sizeof(float), hipMemcpyHostToDevice,
+                              st));
+    SMG_HIP(h, hipStreamSynchronize(st));
+    h->mlp.direct_ready = true;
     return STOKESMG_OK;
 }
 

@@ -25,7 +25,7 @@ struct Capture {
 // workspace unless `r` / `counters` are given (the no-allocation entry point
 // passes its static scratch; counters may then be null).
 int smooth_sweep(stokesmg* h, int level, bool f64, void* x, const void* b, hipStream_t st, const Capture* cap,
-                 void* r = nullptr, int* counters = nullptr, bool own_counters = false);
+                 void* r = nullptr, unsigned long long* counters = nullptr, bool own_counters = false);
 
 // the learned correction of every interior patch of one colour
 int mlp_interior_solve(stokesmg* h, int level, bool f64, void* x, const void* r, int colour, hipStream_t st);

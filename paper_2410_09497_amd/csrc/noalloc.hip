@@ -16,7 +16,7 @@
 
 namespace {
 
-constexpr size_t kCounterBytes = 256;   // two int CG counters, padded to keep the vector 256-byte aligned
+constexpr size_t kCounterBytes = 256;   // two 64-bit CG counters, padded to keep the vector 256-byte aligned
 
 __device__ __align__(256) unsigned char scratch[STOKESMG_NOALLOC_SCRATCH_BYTES];
 
@@ -71,7 +71,7 @@ int patch_smooth_noalloc(stokesmg_t* h, int level, int dtype, void* x, const voi
         return h->fail(STOKESMG_EINVAL, "x, b and the workspace must not overlap");
     void* base = nullptr;
     SMG_HIP(h, scratch_ptr(&base));
-    int* counters = static_cast<int*>(base);
+    unsigned long long* counters = static_cast<unsigned long long*>(base);
     void* r = static_cast<unsigned char*>(base) + kCounterBytes;
     if (ranges_overlap(x, bytes, base, STOKESMG_NOALLOC_SCRATCH_BYTES) ||
         ranges_overlap(b, bytes, base, STOKESMG_NOALLOC_SCRATCH_BYTES))
@@ -79,14 +79,14 @@ int patch_smooth_noalloc(stokesmg_t* h, int level, int dtype, void* x, const voi
     const bool f64 = dtype == STOKESMG_F64;
     hipStream_t st = static_cast<hipStream_t>(stream);
     // the counters start at zero on every call (a fill kernel: safe under graph capture)
-    SMG_HIP(h, smg::launch_zero(true, counters, 1, st));
+    SMG_HIP(h, smg::launch_zero(true, counters, 2, st));
     for (int s = 0; s < n_sweeps; ++s)
         if (int rc = smg::smooth_sweep(h, level, f64, x, b, st, nullptr, r, counters, true)) return rc;
     if (cg_iterations) {
-        int c[2] = {0, 0};
+        unsigned long long c[2] = {0, 0};
         SMG_HIP(h, hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
         SMG_HIP(h, hipStreamSynchronize(st));
-        *cg_iterations = c[0];
+        *cg_iterations = int64_t(c[0]);
     }
     return STOKESMG_OK;
 }

@@ -254,10 +254,22 @@ struct PatchIndex {
     }
 };
 
+// Warm start of the Schur CG (interior patches only): the patch pressure
+// predicted by the network, normalized as in its training pairs --
+// row b of y holds (U, h P) / s for the interior patch p0 + b of the colour,
+// the pressure part at offset 3 NV, and s[b] the input scale.
+struct PatchWarm {
+    const float* y = nullptr;
+    const float* s = nullptr;
+    int ldy = 0, p0 = 0;
+    int cnt[3] = {0, 0, 0};   // interior vertices per direction of the colour
+};
+
 template <int K, typename T, int NTP = 0>
 __global__ void __launch_bounds__((PatchShape<K, NTP>::NT))
 patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restrict__ tab, int n, int colour,
-                   int cntx, int cnty, T cg_rtol, int cg_maxit, int* __restrict__ counters, int boundary_only) {
+                   int cntx, int cnty, T cg_rtol, int cg_maxit, unsigned long long* __restrict__ counters, int boundary_only,
+                   PatchWarm warm) {
     using P = PatchShape<K, NTP>;
     using PT = PatchTab<K>;
     constexpr int NV = P::NV, NP = P::NP, ND = P::ND, NW = P::NW;
@@ -271,9 +283,19 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     // vertex of this workgroup: coordinates of parity (colour bit) in 1..n-1
     const int px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
     const int b = blockIdx.x;
-    const int vx = (px ? 1 : 2) + 2 * (b % cntx);
-    const int vy = (py ? 1 : 2) + 2 * ((b / cntx) % cnty);
-    const int vz = (pz ? 1 : 2) + 2 * (b / (cntx * cnty));
+    const bool warm_start = warm.y != nullptr;
+    int vx, vy, vz;
+    if (warm_start) {
+        // interior patch p0 + b of the colour (2 <= v_d <= n - 2), in the order of the network's batch
+        const int p = warm.p0 + b;
+        vx = (px ? 3 : 2) + 2 * (p % warm.cnt[0]);
+        vy = (py ? 3 : 2) + 2 * ((p / warm.cnt[0]) % warm.cnt[1]);
+        vz = (pz ? 3 : 2) + 2 * (p / (warm.cnt[0] * warm.cnt[1]));
+    } else {
+        vx = (px ? 1 : 2) + 2 * (b % cntx);
+        vy = (py ? 1 : 2) + 2 * ((b / cntx) % cnty);
+        vz = (pz ? 1 : 2) + 2 * (b / (cntx * cnty));
+    }
     const int tx = (vx == 1 ? 1 : 0) + (vx == n - 1 ? 2 : 0);
     const int ty = (vy == 1 ? 1 : 0) + (vy == n - 1 ? 2 : 0);
     const int tz = (vz == 1 ? 1 : 0) + (vz == n - 1 ? 2 : 0);
@@ -334,7 +356,38 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
         }
         rr = block_sum<NW>(s2, red);
     }
-    const T rr0 = rr;
+    const T rr0 = rr;   // the cold-start residual: the stopping test refers to it in both cases
+    if (warm_start) {
+        // P = predicted pressure (mean zero), R = rhs - S P, D = R
+        const T ih = T(n);   // 1 / h
+        const float sc = warm.s[b];
+        const float* yrow = warm.y + size_t(b) * warm.ldy + 3 * NV;
+        T s = 0;
+        for (int i = tid; i < NP; i += P::NT) {
+            const T v = T(sc) * T(yrow[i]) * ih;
+            Pv[i] = v;
+            s += v;
+        }
+        const T pmean = block_sum<NW>(s, red) / T(NP);
+        for (int i = tid; i < NP; i += P::NT) Pv[i] -= pmean;
+        __syncthreads();
+        apply_BT<K, NTP, T>(Pv, V1, Dp, md, codes);
+        __syncthreads();
+        fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir, codes);
+        apply_B<K, NTP, T>(V1, Q, Dp, md);
+        __syncthreads();
+        T sq = 0;
+        for (int i = tid; i < NP; i += P::NT) sq += Q[i];
+        const T qmean = block_sum<NW>(sq, red) / T(NP);
+        T s2 = 0;
+        for (int i = tid; i < NP; i += P::NT) {
+            const T v = R[i] - (Q[i] - qmean);
+            R[i] = v;
+            Dv[i] = v;
+            s2 += v * v;
+        }
+        rr = block_sum<NW>(s2, red);
+    }
     // CG in precision T cannot reduce the residual much below 16 eps: a tighter request is raised
     // to that level (1.9e-6 in FP32, 3.6e-15 in FP64) instead of iterating on rounding noise
     constexpr T kFloor = T(16) * (sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7));
@@ -397,8 +450,8 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     }
     for (int i = tid; i < NP; i += P::NT) x[gi.template pres<K>(i)] += Pv[i];
     if (counters && tid == 0) {
-        atomicAdd(counters, it);
-        atomicAdd(counters + 1, 1);
+        atomicAdd(counters, static_cast<unsigned long long>(it));
+        atomicAdd(counters + 1, 1ull);
     }
 }
 

@@ -220,11 +220,11 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
     } restore{h, solver0};
     int64_t it0 = 0, so0 = 0;
     {
-        int c[2];
+        unsigned long long c[2];
         SMG_HIP(h, hipMemcpyAsync(c, h->ws + h->cg_counter, sizeof(c), hipMemcpyDeviceToHost, st));
         SMG_HIP(h, hipStreamSynchronize(st));
-        it0 = c[0];
-        so0 = c[1];
+        it0 = int64_t(c[0]);
+        so0 = int64_t(c[1]);
     }
 
     double bnorm = 0.0;
@@ -358,11 +358,11 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
         const double last = hist.back();
         info->nu = (it > 0 && last > 0) ? -8.0 / (std::log10(last) / it) : 0.0;
         for (size_t i = 0; i < hist.size() && i < STOKESMG_MAX_HISTORY; ++i) info->history[i] = hist[i];
-        int c[2];
+        unsigned long long c[2];
         SMG_HIP(h, hipMemcpyAsync(c, h->ws + h->cg_counter, sizeof(c), hipMemcpyDeviceToHost, st));
         SMG_HIP(h, hipStreamSynchronize(st));
-        info->cg_iterations = c[0] - it0;
-        info->local_solves = c[1] - so0;
+        info->cg_iterations = int64_t(c[0]) - it0;
+        info->local_solves = int64_t(c[1]) - so0;
         info->seconds = std::chrono::duration<double>(t1 - t0).count();
         info->fallback_iteration = fallback_at;
     }
