@@ -23,10 +23,12 @@ from exact V-cycles on 32^3 cells).
 
 Third part, `c1`: the operator and the smoother for every degree k = 1..5 in
 FP64 and FP32 at 64^3 cells (K applications and a few sweeps per cell).
+Fourth part, `error_vs_time`: L2 errors against time to solution for
+k = 1..4 on 16^3 .. 128^3 cells.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 2] [--n 64]
                        [--dtype f64|f32] [--no-cpu-baseline] [--no-solve]
-                       [--solve-n 128] [--no-c1] [--c1-sweeps 3]
+                       [--solve-n 128] [--no-c1] [--c1-sweeps 3] [--no-k3] [--no-f4]
 """
 import argparse
 import hashlib
@@ -72,21 +74,21 @@ def measured_traffic(k, n, dtype, ndof):
 
 
 def cpu_baseline(k):
-    """The oracle's operator (element-by-element local matrices, NumPy) on
-    32^3 cells at the same degree: a bounded sample (1/8 of the 64^3 mesh)."""
+    """The oracle's operator (element matrices, NumPy FP64) on 32^3 cells at the
+    same degree: a bounded sample (1/8 of the 64^3 mesh).  `cores` is the
+    number of cores the oracle kept busy: process CPU time over wall time of
+    the timed repetitions (NumPy's BLAS runs the element products on several
+    threads; the scatter-add runs on one)."""
     import numpy as np
     from oracle.stokes import Stokes
     from paper_2410_09497_amd.synth import uniform_vector
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
     n = 32
     S = Stokes(n, k)
     x = uniform_vector(S.ndof, seed=k)
     S.local_matrices()
+    S.apply(x)
     reps = 0
+    c0 = os.times()
     t0 = time.perf_counter()
     while True:
         S.apply(x)
@@ -94,9 +96,12 @@ def cpu_baseline(k):
         el = time.perf_counter() - t0
         if el > 10.0 or reps >= 3:
             break
-    return {"value": S.ndof * reps / el, "unit": "DoF/s", "cores": int(threads), "kind": "oracle",
+    c1 = os.times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    cores = cpu / el
+    return {"value": S.ndof * reps / el, "unit": "DoF/s", "cores": round(cores, 1), "kind": "oracle",
             "sample": f"oracle stokes apply (local element matrices, NumPy FP64) on {n}^3 cells, k={k} "
-                      f"({S.ndof} unknowns), {reps} repetitions, {el:.1f} s; host has "
+                      f"({S.ndof} unknowns), {reps} repetitions, {el:.1f} s wall, {cpu:.1f} s CPU; host has "
                       f"{len(os.sched_getaffinity(0))} usable cores"}
 
 
@@ -141,11 +146,27 @@ def c1_section(dev, n, steps, sweeps, log):
             torch.cuda.synchronize()
             t_sweep = e0.elapsed_time(e1) * 1e-3 / sweeps
             its, solves = mg.cg_stats(reset=True)
-            out[f"k{k}_{dt}"] = {"unknowns": ndof, "apply_ms": t_apply * 1e3, "apply_GDoF_s": ndof / t_apply / 1e9,
-                                 "apply_hbm_frac": 2 * es * ndof / t_apply / 1e9 / HBM_PEAK_GBS,
-                                 "sweep_ms": t_sweep * 1e3, "sweep_GDoF_s": ndof / t_sweep / 1e9,
-                                 "sweep_avg_local_cg": its / max(solves, 1)}
-            log(f"[bench] C1 k={k} {dt}: apply {t_apply * 1e3:.3f} ms, sweep {t_sweep * 1e3:.1f} ms")
+            cell = {"unknowns": ndof, "apply_ms": t_apply * 1e3, "apply_GDoF_s": ndof / t_apply / 1e9,
+                    "apply_hbm_frac": 2 * es * ndof / t_apply / 1e9 / HBM_PEAK_GBS,
+                    "sweep_ms": t_sweep * 1e3, "sweep_GDoF_s": ndof / t_sweep / 1e9,
+                    "sweep_avg_local_cg": its / max(solves, 1)}
+            if k <= 3 and dt == "f32":
+                # the same sweeps with the Direct solver on the interior patches (BF16 operands on MFMA)
+                mg.mlp_setup(131072)
+                mg.direct_setup()
+                mg.set_local_solver("direct", "bf16")
+                xsm.zero_()
+                mg.smooth(xsm, b, sweeps=1)
+                xsm.zero_()
+                e0.record(stream)
+                mg.smooth(xsm, b, sweeps=sweeps)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                mg.set_local_solver("exact")
+                cell["sweep_direct_bf16_ms"] = e0.elapsed_time(e1) / sweeps
+            out[f"k{k}_{dt}"] = cell
+            log(f"[bench] C1 k={k} {dt}: apply {t_apply * 1e3:.3f} ms, sweep {t_sweep * 1e3:.1f} ms"
+                + (f", direct sweep {cell['sweep_direct_bf16_ms']:.1f} ms" if "sweep_direct_bf16_ms" in cell else ""))
         del mg, x64
         torch.cuda.empty_cache()
     return out
@@ -270,6 +291,41 @@ def solve_section(dev, k, n_solve, log):
     return out
 
 
+def error_vs_time_section(dev, log):
+    """Error against time to solution (the study of Sec. 3.3's 3D figure of
+    error over solve time): the manufactured sine problem to 1e-8 with the
+    FP32 V-cycle in FP64 FGMRES(8) (interior local solves by the Direct solver
+    on the matrix cores for k <= 3, the Schur CG at k = 4), for k = 1..4 on
+    16^3 .. 128^3 cells; L2 errors of velocity and pressure by the library's
+    quadrature (stokesmg_l2_error)."""
+    import torch
+    from paper_2410_09497_amd import StokesMG
+    out = {"workload": "sine problem to 1e-8, FP32 V-cycle in FP64 FGMRES(8); Direct BF16 interior solves for "
+                       "k <= 3; local Schur CG rtol 1e-3 (<= 15 iterations) elsewhere", "runs": []}
+    for k in (1, 2, 3, 4):
+        for n in (16, 32, 64, 128):
+            if (k == 4 and n > 64) or (k == 3 and n > 128):
+                continue
+            mg = StokesMG(n, k, cg_rtol=1e-3, cg_max_it=15, device=dev)
+            solver = "exact"
+            if k <= 3:
+                mg.mlp_setup(131072)
+                mg.direct_setup()
+                solver = "direct"
+            mg.set_local_solver(solver, "bf16")
+            b = mg.rhs_manufactured()
+            x, info = mg.solve(b, rtol=1e-8, max_it=30, vcycle_dtype="f32", restart=8)
+            eu, ep = mg.l2_error(x)
+            out["runs"].append({"k": k, "n": n, "unknowns": mg.ndof(), "seconds": info["seconds"],
+                                "iterations": info["iterations"], "l2_error_u": eu, "l2_error_p": ep,
+                                "local_solver": solver})
+            log(f"[bench] error-vs-time k={k} n={n}: {info['seconds']:.3f} s, {info['iterations']} steps, "
+                f"|u-u_h| {eu:.3e}, |p-p_h| {ep:.3e}")
+            del mg, x, b
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +340,7 @@ def main():
     ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--c1-sweeps", type=int, default=3)
     ap.add_argument("--no-k3", action="store_true", help="skip the degree-3 solves (C4 at k = 3)")
+    ap.add_argument("--no-f4", action="store_true", help="skip the error-versus-time study")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the method's hot path here is single-GPU "
@@ -376,6 +433,8 @@ def main():
         out["solve"] = solve_section(dev, k, args.solve_n, log)
         if not args.no_k3 and k != 3:
             out["solve_k3"] = solve_section(dev, 3, args.solve_n, log)
+    if not args.no_f4:
+        out["error_vs_time"] = error_vs_time_section(dev, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(k)
     print(json.dumps(out))

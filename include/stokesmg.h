@@ -203,6 +203,14 @@ int solve(stokesmg_t* h, const double* b, double* x, double rtol, int max_it, in
 #define STOKESMG_PROBLEM_SINE 0
 int stokesmg_rhs_manufactured(stokesmg_t* h, int level, int problem, double* b, void* stream);
 
+/* L2 errors ||u - u_h|| (velocity) and ||p - p_h|| (pressure, both with zero
+ * integral mean) over the unit cube of the FP64 level vector x against the
+ * manufactured solution `problem`, by Gauss quadrature with k+3 points per
+ * direction in every cell.  Uses the workspace scratch; synchronizes
+ * `stream`.  For the error-versus-time study of the solver (Sec. 3.3). */
+int stokesmg_l2_error(stokesmg_t* h, int level, int problem, const double* x, double* err_u, double* err_p,
+                      void* stream);
+
 /* Right-hand side (f, phi) of a smooth random body force (FP64 device
  * vector on level `level`), no boundary data, pressure rows zero:
  * f_c(x) = sum_m amp[c][m] cos(pi kappa[c][m] . x + theta[c][m]), c = 0..2,

@@ -308,6 +308,16 @@ class StokesMG:
         self._check(_lib.lib.stokesmg_set_local_solver(self._h, {"exact": 0, "mlp": 1, "mlp_warm": 2, "direct": 3}[solver], self._mode(mode),
                                                        float(damping)))
 
+    def l2_error(self, x, level=-1):
+        """(||u - u_h||, ||p - p_h||) of the FP64 level vector x against the
+        manufactured sine problem (Gauss k+3 per direction, zero-mean pressures)."""
+        level = level % self.n_levels
+        self._vec(x, level, "x")
+        eu, ep = ctypes.c_double(), ctypes.c_double()
+        self._check(_lib.lib.stokesmg_l2_error(self._h, level, 0, x.data_ptr(), ctypes.byref(eu), ctypes.byref(ep),
+                                               self._stream()))
+        return eu.value, ep.value
+
     def direct_matrix(self):
         """The Direct solver's normalized interior map (host, FP64, [out][in])."""
         import numpy as np

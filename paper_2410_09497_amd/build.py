@@ -11,7 +11,7 @@ OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(PKG, "libstokesmg.so")
 
 SOURCES = ["api.cpp", "tables.cpp", "apply.hip", "apply_common.cpp", "apply_k1.hip", "apply_k2.hip", "apply_k3.hip",
-           "apply_k4.hip", "apply_k5.hip", "patch.hip", "mg_tables.cpp", "mg_kernels.hip", "solver.cpp", "mlp.cpp", "mlp_kernels.hip", "noalloc.hip", "direct.cpp"]
+           "apply_k4.hip", "apply_k5.hip", "patch.hip", "mg_tables.cpp", "mg_kernels.hip", "solver.cpp", "mlp.cpp", "mlp_kernels.hip", "noalloc.hip", "direct.cpp", "l2error.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
