@@ -257,18 +257,19 @@ int stokesmg_rhs_fourier(stokesmg_t* h, int level, int n_modes, const int* kappa
                                     from the pressure the network predicts instead of zero, with the
                                     same stopping test (relative to the cold-start residual): the
                                     exact solver judges, the network only saves iterations */
-#define STOKESMG_LOCAL_DIRECT 3  /* the "Direct" solver of Sec. 3.3 on interior patches: the patch
-                                    pseudo-inverse as one dense matrix (the same on every level in
-                                    the normalized variables of the gather), applied to a colour's
-                                    interior patches as one GEMM on the matrix cores (BF16 or FP32
-                                    operands per mlp_mode, FP32 accumulation); the Schur CG on the
-                                    boundary patches.  Needs stokesmg_direct_setup(). */
+#define STOKESMG_LOCAL_DIRECT 3  /* the "Direct" solver of Sec. 3.3 on every patch: the patch
+                                    pseudo-inverse as one dense matrix per patch type (the same on
+                                    every level in the normalized variables of the gather), applied
+                                    to a colour's patches as one grouped GEMM on the matrix cores
+                                    (BF16 or FP32 operands per mlp_mode, FP32 accumulation); no
+                                    local iteration.  Needs stokesmg_direct_setup(). */
 
 /* d (network width in and out) and P (parameter count) for the handle's degree. */
 int mlp_dims(const stokesmg_t* h, int64_t* d, int64_t* n_params);
 
 /* Bytes of the MLP workspace for batches of up to max_rows rows (training
- * batches, or the interior patches of one colour per chunk in the smoother). */
+ * batches, or the patches of one colour per chunk in the smoother); for
+ * degrees 1..3 it includes the Direct solver's 28 d x d FP32 matrices. */
 int mlp_workspace_size(const stokesmg_t* h, int64_t max_rows, size_t* bytes);
 int mlp_set_workspace(stokesmg_t* h, void* dev_ptr, size_t bytes, int64_t max_rows);
 
@@ -317,16 +318,22 @@ int mlp_train(stokesmg_t* h, int mode, const float* X, const float* T, int64_t n
  * parameters; the Direct solver needs stokesmg_direct_setup(). */
 int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode, double mlp_damping);
 
-/* The Direct solver's matrix (Sec. 3.3 "Direct solver", interior patches):
- * t = M x with x = (F / h, G / h^2) and t = (U, h P) for the patch residual
- * (F, G) and its exact correction (U, P) = K_j^+ (F, G); the same on every
- * level.  Built on the host in FP64 from the fast-diagonalization tables via
- * the Schur complement of Sec. 3.2 and checked between two levels.
- * stokesmg_direct_matrix writes it to host memory (d x d doubles, row-major
- * [out][in], d from mlp_dims; no device needed).  stokesmg_direct_setup
- * uploads it (FP32) into the MLP workspace, which must be set (ENOMEM) and
- * has room for it; synchronizes `stream`.  Degrees 1..3 (EUNSUPPORTED). */
-int stokesmg_direct_matrix(const stokesmg_t* h, double* M);
+/* The Direct solver's matrices (Sec. 3.3 "Direct solver"), one per patch
+ * type: t = M x with x = (F / h, G / h^2) and t = (U, h P) for the patch
+ * residual (F, G) and its exact correction (U, P) = K_j^+ (F, G); the same on
+ * every level.  The type says which outer faces of the vertex patch lie on
+ * the domain boundary: type = t_x + 3 t_y + 9 t_z with t_d = 0 (neither),
+ * 1 (the lower face: vertex coordinate 1), 2 (the upper face: vertex n - 1);
+ * type 27 is the single patch of the 2^3-cell mesh (both faces everywhere).
+ * Built on the host in FP64 from the fast-diagonalization tables via the
+ * Schur complement of Sec. 3.2 and checked between two levels.
+ * stokesmg_direct_matrix writes the matrix of one type to host memory (d x d
+ * doubles, row-major [out][in], d from mlp_dims; no device needed; EINVAL
+ * for a type outside 0..27).  stokesmg_direct_setup builds all 28 (on host
+ * threads) and uploads them (FP32) into the MLP workspace, which must be set
+ * (ENOMEM) with at least 128 rows (EINVAL); synchronizes `stream`.  Degrees
+ * 1..3 (EUNSUPPORTED). */
+int stokesmg_direct_matrix(const stokesmg_t* h, int type, double* M);
 int stokesmg_direct_setup(stokesmg_t* h, void* stream);
 
 /* Fallback of the learned solver inside solve(): with the MLP local solver,

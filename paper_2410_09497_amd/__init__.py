@@ -318,12 +318,14 @@ class StokesMG:
                                                self._stream()))
         return eu.value, ep.value
 
-    def direct_matrix(self):
-        """The Direct solver's normalized interior map (host, FP64, [out][in])."""
+    def direct_matrix(self, patch_type=0):
+        """The Direct solver's normalized map of one patch type (host, FP64,
+        [out][in]); type t_x + 3 t_y + 9 t_z with t_d = 0 inside, 1 at the
+        lower and 2 at the upper boundary, 27 for the single patch of n = 2."""
         import numpy as np
         d, _ = self.mlp_dims()
         M = np.empty((d, d), dtype=np.float64)
-        self._check(_lib.lib.stokesmg_direct_matrix(self._h, M.ctypes.data))
+        self._check(_lib.lib.stokesmg_direct_matrix(self._h, int(patch_type), M.ctypes.data))
         return M
 
     def direct_setup(self):

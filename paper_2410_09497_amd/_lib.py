@@ -72,7 +72,7 @@ def _load():
                             ctypes.POINTER(ctypes.c_float), vp]),
         "stokesmg_set_local_solver": (i32, [vp, i32, i32, ctypes.c_double]),
         "stokesmg_set_fallback": (i32, [vp, ctypes.c_double]),
-        "stokesmg_direct_matrix": (i32, [vp, vp]),
+        "stokesmg_direct_matrix": (i32, [vp, i32, vp]),
         "stokesmg_l2_error": (i32, [vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                     vp]),
         "stokesmg_direct_setup": (i32, [vp, vp]),

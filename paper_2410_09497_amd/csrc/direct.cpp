@@ -1,11 +1,15 @@
 // The "Direct" local solver of Sec. 3.3 (the pseudo-inverse of the patch
-// matrix) for interior patches, as one dense matrix per degree.
+// matrix), as one dense matrix per patch type.
 //
-// An interior patch (its 8 cells touch no boundary face) has the patch matrix
-// K_j(h) = [[h A^, h^2 B^T], [h^2 B^, 0]] with level-independent A^, B^ (A_j
-// scales like h, B_j like h^2).  In the normalized variables of the patch
-// gather -- input x = (F / h, G / h^2), output t = (U, h P) -- the exact local
-// solve t = M x has the same matrix M on every level:
+// A vertex patch (8 cells around vertex v) has the patch matrix
+// K_j(h) = [[h A^, h^2 B^T], [h^2 B^, 0]] with A^, B^ independent of the level:
+// A_j scales like h (the interior penalty 2 (k+1)^2 / h included, on interior
+// and boundary faces alike), B_j like h^2.  A^ depends on the patch only
+// through which outer faces lie on the domain boundary, per direction (the
+// four 1D window types of the fast diagonalization); B^ is the same for all.
+// In the normalized variables of the patch gather -- input x = (F / h, G / h^2),
+// output t = (U, h P) -- the exact local solve t = M x therefore has one
+// matrix per type on every level:
 //   M = [[h Kuu, h^2 Kup], [h^2 Kpu, h^3 Kpp]],  K_j^+ = [[Kuu, Kup], [Kpu, Kpp]].
 // K_j^+ is formed through the Schur complement of Sec. 3.2 (with the
 // pseudo-inverse S^+ on mean-zero pressures, which equals the pseudo-inverse
@@ -14,11 +18,16 @@
 // with A^-1 dense from the fast diagonalization (Eqs. inverse2d /
 // fast_inverse extended to 3D) and S^+ = (S + a 1 1^T)^-1 - 1 1^T / (a NP^2)
 // (S is positive definite on mean-zero vectors and S 1 = 0).  Everything in
-// FP64 on the host; M is built from two levels and the two must agree.
+// FP64 on the host; every M is built from two levels and the two must agree.
 #include "direct.hpp"
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <exception>
+#include <mutex>
 #include <stdexcept>
+#include <thread>
 
 #include "tables.hpp"
 
@@ -26,9 +35,33 @@ namespace smg {
 
 namespace {
 
-// A^-1 of velocity component c (dense, NV x NV) from the interior-type FD
-// tables: (S2 x S1 x S0) diag(1 / (l0 + l1 + l2)) (S2 x S1 x S0)^T
-std::vector<double> fd_inverse_dense(const std::vector<double>& t, int k, int c) {
+// C (m x n) = A (m x q) B (q x n), all row-major; the inner loop runs over
+// contiguous columns of B and C
+void matmul(const double* A, const double* B, double* C, int m, int q, int n) {
+    std::fill(C, C + size_t(m) * n, 0.0);
+    for (int i = 0; i < m; ++i) {
+        double* c = C + size_t(i) * n;
+        for (int p = 0; p < q; ++p) {
+            const double a = A[size_t(i) * q + p];
+            if (a == 0.0) continue;
+            const double* b = B + size_t(p) * n;
+            for (int j = 0; j < n; ++j) c[j] += a * b[j];
+        }
+    }
+}
+
+std::vector<double> transpose(const std::vector<double>& A, int m, int n) {
+    std::vector<double> T(size_t(m) * n);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j) T[size_t(j) * m + i] = A[size_t(i) * n + j];
+    return T;
+}
+
+// A^-1 of velocity component c (dense, NV x NV) from the FD tables, with
+// window type ty[d] in the two directions d != c (the continuous window of
+// direction c is the same for every patch):
+//   (S2 x S1 x S0) diag(1 / (l0 + l1 + l2)) (S2 x S1 x S0)^T
+std::vector<double> fd_inverse_dense(const std::vector<double>& t, int k, int c, const int ty[3]) {
     const int nc = 2 * k + 1, nd = 2 * k + 2;
     const int oSC = 0, oLC = nc * nc, oSD = oLC + nc, oLD = oSD + 4 * nd * nd;
     int ext[3];
@@ -36,36 +69,28 @@ std::vector<double> fd_inverse_dense(const std::vector<double>& t, int k, int c)
     const double* L[3];
     for (int d = 0; d < 3; ++d) {
         ext[d] = d == c ? nc : nd;
-        S[d] = d == c ? &t[oSC] : &t[oSD];      // boundary type 0: interior window
-        L[d] = d == c ? &t[oLC] : &t[oLD];
+        S[d] = d == c ? &t[oSC] : &t[oSD + ty[d] * nd * nd];
+        L[d] = d == c ? &t[oLC] : &t[oLD + ty[d] * nd];
     }
     const int nv = ext[0] * ext[1] * ext[2];
     // Q[e][mode] = S0[i0][m0] S1[i1][m1] S2[i2][m2]
-    std::vector<double> Q(size_t(nv) * nv), lam(nv);
+    std::vector<double> Q(size_t(nv) * nv), QD(size_t(nv) * nv);
     for (int m2 = 0; m2 < ext[2]; ++m2)
         for (int m1 = 0; m1 < ext[1]; ++m1)
             for (int m0 = 0; m0 < ext[0]; ++m0) {
                 const int md = m0 + ext[0] * (m1 + ext[1] * m2);
-                lam[md] = L[0][m0] + L[1][m1] + L[2][m2];
+                const double lam = L[0][m0] + L[1][m1] + L[2][m2];
                 for (int i2 = 0; i2 < ext[2]; ++i2)
                     for (int i1 = 0; i1 < ext[1]; ++i1)
                         for (int i0 = 0; i0 < ext[0]; ++i0) {
                             const int e = i0 + ext[0] * (i1 + ext[1] * i2);
-                            Q[size_t(e) * nv + md] =
-                                S[0][i0 * ext[0] + m0] * S[1][i1 * ext[1] + m1] * S[2][i2 * ext[2] + m2];
+                            const double q = S[0][i0 * ext[0] + m0] * S[1][i1 * ext[1] + m1] * S[2][i2 * ext[2] + m2];
+                            Q[size_t(e) * nv + md] = q;
+                            QD[size_t(e) * nv + md] = q / lam;
                         }
             }
-    std::vector<double> Ainv(size_t(nv) * nv, 0.0), QD(size_t(nv) * nv);
-    for (int e = 0; e < nv; ++e)
-        for (int md = 0; md < nv; ++md) QD[size_t(e) * nv + md] = Q[size_t(e) * nv + md] / lam[md];
-    for (int e = 0; e < nv; ++e)
-        for (int f = 0; f < nv; ++f) {
-            double s = 0.0;
-            const double* a = &QD[size_t(e) * nv];
-            const double* b = &Q[size_t(f) * nv];
-            for (int md = 0; md < nv; ++md) s += a[md] * b[md];
-            Ainv[size_t(e) * nv + f] = s;
-        }
+    std::vector<double> Ainv(size_t(nv) * nv);
+    matmul(QD.data(), transpose(Q, nv, nv).data(), Ainv.data(), nv, nv, nv);
     return Ainv;
 }
 
@@ -127,53 +152,39 @@ void spd_inverse(std::vector<double>& A, int n) {
         }
 }
 
-// M (d x d, row-major [out][in]) from the patch tables of a level with cell size h
-std::vector<double> normalized_map(const std::vector<double>& t, int k, double h) {
+// M (d x d, row-major [out][in]) of window types ty from the patch tables of a level with cell size h
+std::vector<double> normalized_map(const std::vector<double>& t, int k, double h, const int ty[3]) {
     const int nc = 2 * k + 1, nd = 2 * k + 2;
     const int nv = nc * nd * nd, nu = 3 * nv, np = nd * nd * nd, d = nu + np;
     std::vector<double> Ai[3];
-    for (int c = 0; c < 3; ++c) Ai[c] = fd_inverse_dense(t, k, c);
+    for (int c = 0; c < 3; ++c) Ai[c] = fd_inverse_dense(t, k, c, ty);
     const std::vector<double> B = divergence_dense(t, k);
+    const std::vector<double> Bt = transpose(B, np, nu);
     // W = A^-1 B^T (nu x np), block diagonal A
-    std::vector<double> W(size_t(nu) * np, 0.0);
+    std::vector<double> W(size_t(nu) * np);
     for (int c = 0; c < 3; ++c)
-        for (int e = 0; e < nv; ++e)
-            for (int p = 0; p < np; ++p) {
-                double s = 0.0;
-                for (int f = 0; f < nv; ++f) s += Ai[c][size_t(e) * nv + f] * B[size_t(p) * nu + c * nv + f];
-                W[size_t(c * nv + e) * np + p] = s;
-            }
+        matmul(Ai[c].data(), Bt.data() + size_t(c) * nv * np, W.data() + size_t(c) * nv * np, nv, nv, np);
     // S = B W (np x np), then S^+
-    std::vector<double> Sp(size_t(np) * np, 0.0);
+    std::vector<double> Sp(size_t(np) * np);
+    matmul(B.data(), W.data(), Sp.data(), np, nu, np);
     double tr = 0.0;
-    for (int p = 0; p < np; ++p)
-        for (int q = 0; q < np; ++q) {
-            double s = 0.0;
-            for (int u = 0; u < nu; ++u) s += B[size_t(p) * nu + u] * W[size_t(u) * np + q];
-            Sp[size_t(p) * np + q] = s;
-        }
     for (int p = 0; p < np; ++p) tr += Sp[size_t(p) * np + p];
     const double a = tr / np / np;
     for (auto& v : Sp) v += a;
     spd_inverse(Sp, np);
     const double corr = 1.0 / (a * double(np) * np);
     for (auto& v : Sp) v -= corr;
-    // WS = W S^+ (nu x np)
-    std::vector<double> WS(size_t(nu) * np, 0.0);
-    for (int u = 0; u < nu; ++u)
-        for (int q = 0; q < np; ++q) {
-            double s = 0.0;
-            for (int p = 0; p < np; ++p) s += W[size_t(u) * np + p] * Sp[size_t(p) * np + q];
-            WS[size_t(u) * np + q] = s;
-        }
+    // WS = W S^+ (nu x np); Kuu = A^-1 - WS W^T
+    std::vector<double> WS(size_t(nu) * np), Kuu(size_t(nu) * nu);
+    matmul(W.data(), Sp.data(), WS.data(), nu, np, np);
+    matmul(WS.data(), transpose(W, nu, np).data(), Kuu.data(), nu, np, nu);
     std::vector<double> M(size_t(d) * d, 0.0);
     const double h2 = h * h, h3 = h2 * h;
     for (int u = 0; u < nu; ++u) {
         const int c = u / nv, e = u - c * nv;
         for (int v = 0; v < nu; ++v) {
-            double s = (v / nv == c) ? Ai[c][size_t(e) * nv + (v - c * nv)] : 0.0;
-            for (int p = 0; p < np; ++p) s -= WS[size_t(u) * np + p] * W[size_t(v) * np + p];
-            M[size_t(u) * d + v] = h * s;                                        // h Kuu
+            const double ai = (v / nv == c) ? Ai[c][size_t(e) * nv + (v - c * nv)] : 0.0;
+            M[size_t(u) * d + v] = h * (ai - Kuu[size_t(u) * nu + v]);            // h Kuu
         }
         for (int q = 0; q < np; ++q) {
             M[size_t(u) * d + nu + q] = h2 * WS[size_t(u) * np + q];            // h^2 Kup
@@ -185,20 +196,63 @@ std::vector<double> normalized_map(const std::vector<double>& t, int k, double h
     return M;
 }
 
-}  // namespace
+void window_types(int type, int ty[3]) {
+    if (type == kDirectTypes - 1) {
+        ty[0] = ty[1] = ty[2] = 3;
+    } else {
+        ty[0] = type % 3;
+        ty[1] = (type / 3) % 3;
+        ty[2] = type / 9;
+    }
+}
 
-std::vector<double> direct_interior_map(const Ref1D& r, double penalty_factor) {
-    const int k = r.k;
-    const std::vector<double> M4 = normalized_map(build_patch_tables(r, 4, penalty_factor), k, 0.25);
-    const std::vector<double> M8 = normalized_map(build_patch_tables(r, 8, penalty_factor), k, 0.125);
+// the map of one type from two levels' tables, which must agree
+std::vector<double> checked_map(const std::vector<double>& t4, const std::vector<double>& t8, int k, int type) {
+    int ty[3];
+    window_types(type, ty);
+    const std::vector<double> M4 = normalized_map(t4, k, 0.25, ty);
+    const std::vector<double> M8 = normalized_map(t8, k, 0.125, ty);
     double scale = 0.0, err = 0.0;
     for (size_t i = 0; i < M4.size(); ++i) {
         scale = std::fmax(scale, std::fabs(M4[i]));
         err = std::fmax(err, std::fabs(M4[i] - M8[i]));
     }
     if (!(err <= 1e-9 * scale))
-        throw std::runtime_error("direct solver: the normalized interior map differs between levels");
+        throw std::runtime_error("direct solver: the normalized patch map differs between levels");
     return M4;
+}
+
+}  // namespace
+
+std::vector<double> direct_type_map(const Ref1D& r, double penalty_factor, int type) {
+    if (type < 0 || type >= kDirectTypes) throw std::invalid_argument("direct solver: patch type out of range");
+    return checked_map(build_patch_tables(r, 4, penalty_factor), build_patch_tables(r, 8, penalty_factor), r.k, type);
+}
+
+std::vector<std::vector<double>> direct_type_maps(const Ref1D& r, double penalty_factor) {
+    const std::vector<double> t4 = build_patch_tables(r, 4, penalty_factor);
+    const std::vector<double> t8 = build_patch_tables(r, 8, penalty_factor);
+    std::vector<std::vector<double>> maps(kDirectTypes);
+    std::atomic<int> next{0};
+    std::exception_ptr err;
+    std::mutex mu;
+    auto work = [&]() {
+        for (int ty = next++; ty < kDirectTypes; ty = next++) {
+            try {
+                maps[ty] = checked_map(t4, t8, r.k, ty);
+            } catch (...) {
+                std::lock_guard<std::mutex> g(mu);
+                if (!err) err = std::current_exception();
+            }
+        }
+    };
+    const int nt = int(std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency())));
+    std::vector<std::thread> pool;
+    for (int i = 1; i < nt; ++i) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+    if (err) std::rethrow_exception(err);
+    return maps;
 }
 
 }  // namespace smg

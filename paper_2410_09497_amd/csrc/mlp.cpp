@@ -56,7 +56,8 @@ size_t layout(stokesmg::Mlp& m, int d, int H, int64_t R) {
     put(m.colp, size_t(smg::kColsumSplit) * (d > H ? d : H) * f);
     put(m.brows, R * sizeof(int));
     put(m.acc, sizeof(double));
-    put(m.direct, size_t(d) * d * f);
+    // the Direct solver's matrices, one per patch type (degrees 1..3 only)
+    put(m.direct, d <= patch_dim(3) ? size_t(smg::kDirectTypes) * d * d * f : 0);
     return off;
 }
 
@@ -181,21 +182,23 @@ int mlp_interior_solve(stokesmg* h, int level, bool f64, void* x, const void* r,
     return STOKESMG_OK;
 }
 
-// interior patches of one colour by the Direct solver: gather, one GEMM with the normalized map on the
-// matrix cores (BF16 or FP32 operands per the MLP mode, FP32 accumulation), scatter
-int direct_interior_solve(stokesmg* h, int level, bool f64, void* x, const void* r, int colour, hipStream_t st) {
+// every patch of one colour by the Direct solver: gather, one GEMM per chunk
+// with each patch type's normalized map on the matrix cores (BF16 or FP32
+// operands per the MLP mode, FP32 accumulation), scatter
+int direct_solve(stokesmg* h, int level, bool f64, void* x, const void* r, int colour, hipStream_t st) {
     auto& m = h->mlp;
     const int n = h->lv[level].n, k = h->cfg.k;
-    const int64_t np = interior_count(n, colour);
+    const PatchGroups pg = colour_groups(n, colour, true);
+    const int total = pg.start[pg.ng];
+    const int chunk = int(m.rows / kGroupAlign) * kGroupAlign;
     const bool bf16 = h->mlp_mode == STOKESMG_MLP_BF16;
     float *X = at<float>(h, m.X), *Y = at<float>(h, m.Y), *s = at<float>(h, m.s);
     const float* Mt = at<float>(h, m.direct);
-    for (int64_t p0 = 0; p0 < np; p0 += m.rows) {
-        const int cnt = int(std::min<int64_t>(m.rows, np - p0));
-        SMG_HIP(h, launch_patch_gather(f64, r, n, k, colour, int(p0), cnt, X, m.d, s, st));
-        SMG_HIP(h, launch_gemm(bf16, Epi::Store, false, false, cnt, m.d, m.d, X, m.d, nullptr, Mt, m.d, Y, m.d,
-                               nullptr, nullptr, 0, nullptr, 0, st));
-        SMG_HIP(h, launch_patch_scatter(f64, x, n, k, colour, int(p0), cnt, Y, m.d, s, 1.0, st));
+    for (int r0 = 0; r0 < total; r0 += chunk) {
+        const int cnt = std::min(chunk, total - r0);
+        SMG_HIP(h, launch_group_gather(f64, r, n, k, pg, r0, cnt, X, m.d, s, st));
+        SMG_HIP(h, launch_gemm_grouped(bf16, cnt, m.d, m.d, X, m.d, Mt, m.d, size_t(m.d) * m.d, Y, m.d, pg, r0, st));
+        SMG_HIP(h, launch_group_scatter(f64, x, n, k, pg, r0, cnt, Y, m.d, s, 1.0, st));
     }
     return STOKESMG_OK;
 }
@@ -256,10 +259,8 @@ int smooth_sweep(stokesmg* h, int level, bool f64, void* x, const void* b, hipSt
             SMG_HIP(h, launch_patch_solve(k, f64, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters,
                                           true, st));
             if (int rc = mlp_interior_solve(h, level, f64, x, r, c, st)) return rc;
-        } else if (direct && interior_count(n, c) > 0) {
-            SMG_HIP(h, launch_patch_solve(k, f64, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters,
-                                          true, st));
-            if (int rc = direct_interior_solve(h, level, f64, x, r, c, st)) return rc;
+        } else if (direct) {
+            if (int rc = direct_solve(h, level, f64, x, r, c, st)) return rc;
         } else if (warm && interior_count(n, c) > 0) {
             SMG_HIP(h, launch_patch_solve(k, f64, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters,
                                           true, st));
@@ -466,11 +467,11 @@ int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode, dou
     return STOKESMG_OK;
 }
 
-int stokesmg_direct_matrix(const stokesmg_t* h, double* M) {
-    if (!h || !M) return STOKESMG_EINVAL;
+int stokesmg_direct_matrix(const stokesmg_t* h, int type, double* M) {
+    if (!h || !M || type < 0 || type >= smg::kDirectTypes) return STOKESMG_EINVAL;
     if (h->cfg.k > 3) return STOKESMG_EUNSUPPORTED;
     try {
-        const std::vector<double> D = smg::direct_interior_map(smg::Ref1D(h->cfg.k), h->cfg.penalty_factor);
+        const std::vector<double> D = smg::direct_type_map(smg::Ref1D(h->cfg.k), h->cfg.penalty_factor, type);
         std::memcpy(M, D.data(), D.size() * sizeof(double));
     } catch (const std::exception&) {
         return STOKESMG_EINVAL;
@@ -481,17 +482,21 @@ int stokesmg_direct_matrix(const stokesmg_t* h, double* M) {
 int stokesmg_direct_setup(stokesmg_t* h, void* stream) {
     if (!h) return STOKESMG_EINVAL;
     if (h->cfg.k > 3) return h->fail(STOKESMG_EUNSUPPORTED, "the Direct solver is built for degrees 1..3");
-    if (!h->mlp.ws) return h->fail(STOKESMG_ENOMEM, "no MLP workspace set (it holds the Direct solver's matrix)");
-    std::vector<double> D;
+    if (!h->mlp.ws) return h->fail(STOKESMG_ENOMEM, "no MLP workspace set (it holds the Direct solver's matrices)");
+    if (h->mlp.rows < smg::kGroupAlign)
+        return h->fail(STOKESMG_EINVAL, "the Direct solver needs an MLP workspace of at least 128 rows");
+    std::vector<std::vector<double>> D;
     try {
-        D = smg::direct_interior_map(smg::Ref1D(h->cfg.k), h->cfg.penalty_factor);
+        D = smg::direct_type_maps(smg::Ref1D(h->cfg.k), h->cfg.penalty_factor);
     } catch (const std::exception& e) {
         return h->fail(STOKESMG_EINVAL, e.what());
     }
     const int d = h->mlp.d;
-    std::vector<float> Mt(size_t(d) * d);   // [in][out], the B operand of the GEMM
-    for (int o = 0; o < d; ++o)
-        for (int i = 0; i < d; ++i) Mt[size_t(i) * d + o] = float(D[size_t(o) * d + i]);
+    const size_t dd = size_t(d) * d;
+    std::vector<float> Mt(smg::kDirectTypes * dd);   // per type [in][out], the B operand of the GEMM
+    for (int t = 0; t < smg::kDirectTypes; ++t)
+        for (int o = 0; o < d; ++o)
+            for (int i = 0; i < d; ++i) Mt[t * dd + size_t(i) * d + o] = float(D[t][size_t(o) * d + i]);
     hipStream_t st = static_cast<hipStream_t>(stream);
     SMG_HIP(h, hipMemcpyAsync(h->mlp.ws + h->mlp.direct, Mt.data(), Mt.size() * sizeof(float), hipMemcpyHostToDevice,
                               st));

@@ -50,6 +50,11 @@ struct GemmArgs {
     int ldz;
     int kslabs_per_split;   // k slabs handled by one blockIdx.z
     size_t split_stride;    // floats between the partial C of consecutive splits
+    int ng;                 // > 0: grouped rows; the tile at row m0 uses B + gmat[g] bstride
+    int grow0;              // group-space row of A's row 0
+    int gstart[kMaxGroups + 1];
+    int gmat[kMaxGroups];
+    size_t bstride;
 };
 
 // One operand tile of R rows x GBK k, R = 32 T: thread t fetches 16 elements
@@ -135,6 +140,14 @@ __global__ void __launch_bounds__(GNT) gemm_kernel(GemmArgs g) {
     const int nslab_total = (g.K + GBK - 1) / GBK;
     const int s_begin = blockIdx.z * g.kslabs_per_split;
     const int s_end = min(nslab_total, s_begin + g.kslabs_per_split);
+    const float* Bsrc = g.B;
+    if (g.ng > 0) {
+        // a tile never straddles two groups: groups start at multiples of kGroupAlign, a multiple of BM
+        const int row = g.grow0 + m0;
+        int gi = 0;
+        while (gi + 1 < g.ng && g.gstart[gi + 1] <= row) ++gi;
+        Bsrc += size_t(g.gmat[gi]) * g.bstride;
+    }
 
     // A element (m, k): !TA -> A[row(m) lda + k] (k contiguous); TA -> A[row(k) lda + m]
     TileLoader<BM, !TA> la;
@@ -149,7 +162,7 @@ __global__ void __launch_bounds__(GNT) gemm_kernel(GemmArgs g) {
 
     if (s_begin < s_end) {
         la.load(g.A, g.lda, g.arows, m0, g.M, s_begin * GBK, g.K, t);
-        lb.load(g.B, g.ldb, nullptr, n0, g.N, s_begin * GBK, g.K, t);
+        lb.load(Bsrc, g.ldb, nullptr, n0, g.N, s_begin * GBK, g.K, t);
     }
     const int fr = lane & 15, fq = lane >> 4;
     for (int s = s_begin; s < s_end; ++s) {
@@ -159,7 +172,7 @@ __global__ void __launch_bounds__(GNT) gemm_kernel(GemmArgs g) {
         __syncthreads();
         if (s + 1 < s_end) {
             la.load(g.A, g.lda, g.arows, m0, g.M, (s + 1) * GBK, g.K, t);
-            lb.load(g.B, g.ldb, nullptr, n0, g.N, (s + 1) * GBK, g.K, t);
+            lb.load(Bsrc, g.ldb, nullptr, n0, g.N, (s + 1) * GBK, g.K, t);
         }
         if constexpr (sizeof(TOP) == 2) {
             bf16x8 a[TI], b[TJ];
@@ -289,6 +302,27 @@ hipError_t launch_gemm(bool bf16, Epi epi, bool ta, bool tb, int M, int N, int K
     return hipGetLastError();
 }
 
+hipError_t launch_gemm_grouped(bool bf16, int rows, int N, int K, const float* A, int lda, const float* B, int ldb,
+                               size_t bstride, float* C, int ldc, const PatchGroups& pg, int row0, hipStream_t st) {
+    if (rows <= 0 || N <= 0 || pg.ng <= 0) return hipSuccess;
+    if (row0 % kGroupAlign != 0) return hipErrorInvalidValue;
+    GemmArgs g{rows, N, K, A, lda, nullptr, B, ldb, C, ldc, nullptr, nullptr, 0, 0, 0};
+    g.kslabs_per_split = std::max(1, (K + GBK - 1) / GBK);
+    g.ng = pg.ng;
+    g.grow0 = row0;
+    for (int i = 0; i <= pg.ng; ++i) g.gstart[i] = pg.start[i];
+    for (int i = 0; i < pg.ng; ++i) g.gmat[i] = pg.mat[i];
+    g.bstride = bstride;
+    static_assert(kGroupAlign % 128 == 0, "a row tile must not straddle two groups");
+    const bool big = size_t((rows + 127) / 128) * ((N + 127) / 128) >= 512;
+    const int bt = big ? 128 : 64;
+    const dim3 grid((N + bt - 1) / bt, (rows + bt - 1) / bt, 1);
+    if (big) return bf16 ? gemm_dispatch_t<__bf16, 4, 4, Epi::Store>(false, false, g, grid, st)
+                         : gemm_dispatch_t<float, 4, 4, Epi::Store>(false, false, g, grid, st);
+    return bf16 ? gemm_dispatch_t<__bf16, 2, 2, Epi::Store>(false, false, g, grid, st)
+                : gemm_dispatch_t<float, 2, 2, Epi::Store>(false, false, g, grid, st);
+}
+
 // ---------------------------------------------------------------- loss, sums, Adam
 
 namespace {
@@ -388,26 +422,60 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, f
 
 // ---------------------------------------------------------------- patch gather / scatter
 
+PatchGroups colour_groups(int n, int colour, bool all_types) {
+    PatchGroups pg{};
+    struct Range {
+        int first, cnt, type;
+    };
+    Range r1[3][3];
+    int nr[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+        const int par = (colour >> d) & 1;
+        const int ci = interior_count_1d(n, par);
+        if (!all_types) {
+            if (ci > 0) r1[d][nr[d]++] = {par ? 3 : 2, ci, 0};
+        } else if (n == 2) {
+            if (par == 1) r1[d][nr[d]++] = {1, 1, 3};
+        } else if (n >= 3) {
+            if (par == 1) r1[d][nr[d]++] = {1, 1, 1};
+            if (ci > 0) r1[d][nr[d]++] = {par ? 3 : 2, ci, 0};
+            if (((n - 1) & 1) == par) r1[d][nr[d]++] = {n - 1, 1, 2};
+        }
+    }
+    int row = 0;
+    for (int c = 0; c < nr[2]; ++c)
+        for (int b = 0; b < nr[1]; ++b)
+            for (int a = 0; a < nr[0]; ++a) {
+                const Range* rg[3] = {&r1[0][a], &r1[1][b], &r1[2][c]};
+                const int g = pg.ng++;
+                pg.start[g] = row;
+                int count = 1;
+                for (int d = 0; d < 3; ++d) {
+                    pg.first[g][d] = rg[d]->first;
+                    pg.cnt[g][d] = rg[d]->cnt;
+                    count *= rg[d]->cnt;
+                }
+                pg.mat[g] = rg[0]->type == 3 ? 27 : rg[0]->type + 3 * rg[1]->type + 9 * rg[2]->type;
+                row += all_types ? (count + kGroupAlign - 1) / kGroupAlign * kGroupAlign : count;
+            }
+    pg.start[pg.ng] = row;
+    return pg;
+}
+
 namespace {
 
 struct PatchGeo {
     int n, k, lc, m, nvel, size, N1;
     size_t nc;
-    int cnt[3], first[3];
 };
 
-__host__ PatchGeo make_geo(int n, int k, int colour) {
+__host__ PatchGeo make_geo(int n, int k) {
     PatchGeo g;
     g.n = n; g.k = k; g.lc = 2 * k + 1; g.m = 2 * k + 2;
     g.nvel = g.lc * g.m * g.m;
     g.size = 3 * g.nvel + g.m * g.m * g.m;
     g.N1 = n * (k + 1);
     g.nc = size_t(g.N1 - 1) * g.N1 * g.N1;
-    for (int d = 0; d < 3; ++d) {
-        const int par = (colour >> d) & 1;
-        g.cnt[d] = interior_count_1d(n, par);
-        g.first[d] = par ? 3 : 2;
-    }
     return g;
 }
 
@@ -428,11 +496,17 @@ __device__ inline size_t patch_index(const PatchGeo& g, const int v[3], int q, b
     return 3 * g.nc + (i0 + base0) + size_t(g.N1) * ((i1 + base1) + size_t(g.N1) * (i2 + base2));
 }
 
-__device__ inline void patch_vertex(const PatchGeo& g, int p, int v[3]) {
-    const int a0 = p % g.cnt[0], a1 = (p / g.cnt[0]) % g.cnt[1], a2 = p / (g.cnt[0] * g.cnt[1]);
-    v[0] = g.first[0] + 2 * a0;
-    v[1] = g.first[1] + 2 * a1;
-    v[2] = g.first[2] + 2 * a2;
+// vertex of row `row` of a grouped row space; false for a padding row (uniform over a workgroup)
+__device__ inline bool group_vertex(const PatchGroups& pg, int row, int v[3]) {
+    int gi = 0;
+    while (gi + 1 < pg.ng && pg.start[gi + 1] <= row) ++gi;
+    const int p = row - pg.start[gi];
+    const int c0 = pg.cnt[gi][0], c1 = pg.cnt[gi][1];
+    if (p >= c0 * c1 * pg.cnt[gi][2]) return false;
+    v[0] = pg.first[gi][0] + 2 * (p % c0);
+    v[1] = pg.first[gi][1] + 2 * ((p / c0) % c1);
+    v[2] = pg.first[gi][2] + 2 * (p / (c0 * c1));
+    return true;
 }
 
 __device__ inline double block_sum(double x, double* red) {
@@ -448,11 +522,17 @@ __device__ inline double block_sum(double x, double* red) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) patch_gather_kernel(const T* __restrict__ r, PatchGeo g, int p0,
-                                                           float* __restrict__ X, int ldx, float* __restrict__ s) {
+__global__ void __launch_bounds__(256) patch_gather_kernel(const T* __restrict__ r, PatchGeo g, PatchGroups pg,
+                                                           int r0, float* __restrict__ X, int ldx,
+                                                           float* __restrict__ s) {
     __shared__ double red[256];
+    float* row = X + size_t(blockIdx.x) * ldx;
     int v[3];
-    patch_vertex(g, p0 + blockIdx.x, v);
+    if (!group_vertex(pg, r0 + blockIdx.x, v)) {
+        for (int q = threadIdx.x; q < g.size; q += 256) row[q] = 0.0f;
+        if (threadIdx.x == 0) s[blockIdx.x] = 0.0f;
+        return;
+    }
     const double ih = g.n, ih2 = double(g.n) * g.n;
     double acc = 0.0;
     for (int q = threadIdx.x; q < g.size; q += 256) {
@@ -463,7 +543,6 @@ __global__ void __launch_bounds__(256) patch_gather_kernel(const T* __restrict__
     }
     const double nrm = sqrt(block_sum(acc, red));
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    float* row = X + size_t(blockIdx.x) * ldx;
     for (int q = threadIdx.x; q < g.size; q += 256) {
         bool pres;
         const size_t gi = patch_index(g, v, q, pres);
@@ -473,17 +552,17 @@ __global__ void __launch_bounds__(256) patch_gather_kernel(const T* __restrict__
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) patch_scatter_kernel(T* __restrict__ x, PatchGeo g, int p0,
+__global__ void __launch_bounds__(256) patch_scatter_kernel(T* __restrict__ x, PatchGeo g, PatchGroups pg, int r0,
                                                             const float* __restrict__ Y, int ldy,
                                                             const float* __restrict__ s, double omega) {
     __shared__ double red[256];
     int v[3];
-    patch_vertex(g, p0 + blockIdx.x, v);
+    if (!group_vertex(pg, r0 + blockIdx.x, v)) return;
     const double sc = omega * double(s[blockIdx.x]);
     if (sc == 0.0) return;   // uniform over the workgroup: no barrier reached yet
     const float* row = Y + size_t(blockIdx.x) * ldy;
     // the exact correction K_j^+ R_j r has zero coefficient mean in the patch
-    // pressure (it is orthogonal to the kernel of K_j): project the learned one
+    // pressure (it is orthogonal to the kernel of K_j): project the computed one
     double ps = 0.0;
     for (int q = 3 * g.nvel + threadIdx.x; q < g.size; q += 256) ps += row[q];
     const double pmean = block_sum(ps, red) / double(g.size - 3 * g.nvel);
@@ -497,14 +576,18 @@ __global__ void __launch_bounds__(256) patch_scatter_kernel(T* __restrict__ x, P
 
 template <typename T>
 __global__ void __launch_bounds__(256) patch_gather_diff_kernel(const T* __restrict__ xn, const T* __restrict__ xo,
-                                                                PatchGeo g, int p0, float* __restrict__ Tt, int ldt,
+                                                                PatchGeo g, PatchGroups pg, int r0,
+                                                                float* __restrict__ Tt, int ldt,
                                                                 const float* __restrict__ s) {
+    float* row = Tt + size_t(blockIdx.x) * ldt;
     int v[3];
-    patch_vertex(g, p0 + blockIdx.x, v);
+    if (!group_vertex(pg, r0 + blockIdx.x, v)) {
+        for (int q = threadIdx.x; q < g.size; q += 256) row[q] = 0.0f;
+        return;
+    }
     const float sc = s[blockIdx.x];
     const double inv = sc > 0.0f ? 1.0 / double(sc) : 0.0;
     const double h = 1.0 / g.n;
-    float* row = Tt + size_t(blockIdx.x) * ldt;
     for (int q = threadIdx.x; q < g.size; q += 256) {
         bool pres;
         const size_t gi = patch_index(g, v, q, pres);
@@ -514,36 +597,49 @@ __global__ void __launch_bounds__(256) patch_gather_diff_kernel(const T* __restr
 
 }  // namespace
 
+hipError_t launch_group_gather(bool f64, const void* r, int n, int k, const PatchGroups& pg, int r0, int rows,
+                               float* X, int ldx, float* s, hipStream_t st) {
+    if (rows <= 0 || pg.ng <= 0) return hipSuccess;
+    const PatchGeo g = make_geo(n, k);
+    if (f64) hipLaunchKernelGGL(patch_gather_kernel<double>, dim3(rows), dim3(256), 0, st,
+                                static_cast<const double*>(r), g, pg, r0, X, ldx, s);
+    else hipLaunchKernelGGL(patch_gather_kernel<float>, dim3(rows), dim3(256), 0, st, static_cast<const float*>(r), g,
+                            pg, r0, X, ldx, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_scatter(bool f64, void* x, int n, int k, const PatchGroups& pg, int r0, int rows,
+                                const float* Y, int ldy, const float* s, double omega, hipStream_t st) {
+    if (rows <= 0 || pg.ng <= 0) return hipSuccess;
+    const PatchGeo g = make_geo(n, k);
+    if (f64) hipLaunchKernelGGL(patch_scatter_kernel<double>, dim3(rows), dim3(256), 0, st, static_cast<double*>(x), g,
+                                pg, r0, Y, ldy, s, omega);
+    else hipLaunchKernelGGL(patch_scatter_kernel<float>, dim3(rows), dim3(256), 0, st, static_cast<float*>(x), g, pg,
+                            r0, Y, ldy, s, omega);
+    return hipGetLastError();
+}
+
 hipError_t launch_patch_gather(bool f64, const void* r, int n, int k, int colour, int p0, int np, float* X, int ldx,
                                float* s, hipStream_t st) {
-    const PatchGeo g = make_geo(n, k, colour);
-    if (np <= 0) return hipSuccess;
-    if (f64) hipLaunchKernelGGL(patch_gather_kernel<double>, dim3(np), dim3(256), 0, st,
-                                static_cast<const double*>(r), g, p0, X, ldx, s);
-    else hipLaunchKernelGGL(patch_gather_kernel<float>, dim3(np), dim3(256), 0, st, static_cast<const float*>(r), g,
-                            p0, X, ldx, s);
-    return hipGetLastError();
+    return launch_group_gather(f64, r, n, k, colour_groups(n, colour, false), p0, np, X, ldx, s, st);
 }
 
 hipError_t launch_patch_scatter(bool f64, void* x, int n, int k, int colour, int p0, int np, const float* Y, int ldy,
                                 const float* s, double omega, hipStream_t st) {
-    const PatchGeo g = make_geo(n, k, colour);
-    if (np <= 0) return hipSuccess;
-    if (f64) hipLaunchKernelGGL(patch_scatter_kernel<double>, dim3(np), dim3(256), 0, st, static_cast<double*>(x), g,
-                                p0, Y, ldy, s, omega);
-    else hipLaunchKernelGGL(patch_scatter_kernel<float>, dim3(np), dim3(256), 0, st, static_cast<float*>(x), g, p0,
-                            Y, ldy, s, omega);
-    return hipGetLastError();
+    return launch_group_scatter(f64, x, n, k, colour_groups(n, colour, false), p0, np, Y, ldy, s, omega, st);
 }
 
 hipError_t launch_patch_gather_diff(bool f64, const void* xnew, const void* xold, int n, int k, int colour, int p0,
                                     int np, float* T, int ldt, const float* s, hipStream_t st) {
-    const PatchGeo g = make_geo(n, k, colour);
     if (np <= 0) return hipSuccess;
+    const PatchGeo g = make_geo(n, k);
+    const PatchGroups pg = colour_groups(n, colour, false);
+    if (pg.ng <= 0) return hipSuccess;
     if (f64) hipLaunchKernelGGL(patch_gather_diff_kernel<double>, dim3(np), dim3(256), 0, st,
-                                static_cast<const double*>(xnew), static_cast<const double*>(xold), g, p0, T, ldt, s);
+                                static_cast<const double*>(xnew), static_cast<const double*>(xold), g, pg, p0, T, ldt,
+                                s);
     else hipLaunchKernelGGL(patch_gather_diff_kernel<float>, dim3(np), dim3(256), 0, st,
-                            static_cast<const float*>(xnew), static_cast<const float*>(xold), g, p0, T, ldt, s);
+                            static_cast<const float*>(xnew), static_cast<const float*>(xold), g, pg, p0, T, ldt, s);
     return hipGetLastError();
 }
 

@@ -49,6 +49,39 @@ hipError_t launch_colsum(const float* G, int ldg, int rows, int cols, float* par
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t st);
 
+// The vertex patches of one colour in groups, one patch type per group: group
+// g holds the vertices (first[g][0] + 2 a, first[g][1] + 2 b, first[g][2] + 2 c),
+// a < cnt[g][0], b < cnt[g][1], c < cnt[g][2], in lexicographic order (a
+// fastest), as rows start[g] .. start[g] + count - 1 of a row space; mat[g] is
+// the type index t_0 + 3 t_1 + 9 t_2 (t_d = 1: vertex 1, 2: vertex n - 1,
+// 0: neither; 27: the single patch of n = 2).  all_types = false: the interior
+// patches only, one group from row 0 (rows p0 .. of the interior launchers).
+// all_types = true: every patch of the colour, each group padded to a
+// multiple of kGroupAlign rows (padding rows gather as zero with s = 0).
+constexpr int kMaxGroups = 27;
+constexpr int kGroupAlign = 128;
+struct PatchGroups {
+    int ng;
+    int start[kMaxGroups + 1];
+    int first[kMaxGroups][3];
+    int cnt[kMaxGroups][3];
+    int mat[kMaxGroups];
+};
+PatchGroups colour_groups(int n, int colour, bool all_types);
+
+// C[rows x N] = A B_g for the rows of a grouped row space (colour_groups with
+// all_types): A's row i is row row0 + i of that space (row0 a multiple of
+// kGroupAlign) and uses B_g = B + mat[g] bstride, K x N row-major.  Epi::Store.
+hipError_t launch_gemm_grouped(bool bf16, int rows, int N, int K, const float* A, int lda, const float* B, int ldb,
+                               size_t bstride, float* C, int ldc, const PatchGroups& pg, int row0, hipStream_t st);
+
+// Rows r0 .. r0+rows-1 of a grouped row space, patch-local vectors of a level
+// vector (row q of X / Y belongs to row r0 + q); the same scaling as below.
+hipError_t launch_group_gather(bool f64, const void* r, int n, int k, const PatchGroups& pg, int r0, int rows,
+                               float* X, int ldx, float* s, hipStream_t st);
+hipError_t launch_group_scatter(bool f64, void* x, int n, int k, const PatchGroups& pg, int r0, int rows,
+                                const float* Y, int ldy, const float* s, double omega, hipStream_t st);
+
 // Interior patches p0 .. p0+np-1 of one colour: patch-local vectors of a
 // level vector (row q of X / Y / T belongs to patch p0 + q).
 //   gather:  X[q] = (R_j r scaled by 1/h (velocity) and 1/h^2 (pressure)) / s_q,

@@ -1,7 +1,8 @@
-"""The Direct local solver (Sec. 3.3) on the matrix cores: interior patches
-by one GEMM per batch with the normalized patch pseudo-inverse, boundary
-patches by the Schur CG.  Against the oracle's smoother with pseudo-inverse
-local solves on every patch, and inside the mixed-precision solve."""
+"""The Direct local solver (Sec. 3.3) on the matrix cores: every patch of a
+colour by one grouped GEMM per chunk with the normalized pseudo-inverse of
+its patch type (interior, face, edge, corner; the single patch of n = 2).
+Against the oracle's smoother with pseudo-inverse local solves on every
+patch, and inside the mixed-precision solve."""
 import numpy as np
 import pytest
 
@@ -13,23 +14,33 @@ from paper_2410_09497_amd.synth import uniform_vector
 pytestmark = pytest.mark.gpu
 
 
-def _direct_mg(n, k, levels=None, cg_rtol=1e-12, cg_max_it=300):
+def _direct_mg(n, k, levels=None, cg_rtol=1e-12, cg_max_it=300, rows=4096):
     mg = StokesMG(n, k, n_levels=levels, cg_rtol=cg_rtol, cg_max_it=cg_max_it)
-    mg.mlp_setup(4096)
+    mg.mlp_setup(rows)
     mg.direct_setup()
     return mg
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
-def test_direct_sweep_matches_oracle(k):
-    """One sweep at 8^3 cells (interior patches 2 <= v <= 6).  The GEMM
-    rounds the normalized residuals and the matrix to its operand precision
-    and accumulates in FP32.  FP32 operands (rounding 2^-24) leave about 5e-8
-    relative error in the sweep's correction (bound 1e-6); BF16 operands
-    (rounding 2^-9 = 2e-3 per operand, errors of independent sign over
-    d >= 208 terms) about 2e-4 (bound: one BF16 rounding unit, 2e-3)."""
+CASES = [(8, 1, 4096), (8, 2, 4096), (8, 3, 4096),
+         # chunks of 128 rows: every group (padded to 128 rows) in a chunk of its own
+         (8, 1, 128),
+         # n = 4: every patch touches the boundary (all 27 types, vertices 1..3)
+         (4, 2, 4096),
+         # n = 2: the single patch, boundary on all six outer faces
+         (2, 1, 4096), (2, 2, 4096)]
+
+
+@pytest.mark.parametrize("n,k,rows", CASES)
+def test_direct_sweep_matches_oracle(n, k, rows):
+    """One sweep.  The GEMM rounds the normalized residuals and the matrix to
+    its operand precision and accumulates in FP32; every patch of the sweep
+    goes through it.  Each product term carries at most one rounding of
+    each operand, 2 u relative at first order, and the errors of the d terms
+    have independent signs.  FP32 operands (u = 2^-24) leave 2e-7 .. 4e-7
+    relative error in the sweep's correction (bound 1e-6, FP32 accumulation
+    and the eight colours included); BF16 operands (u = 2^-9) 1.3e-3 ..
+    2.8e-3 (bound: the first-order worst case of one term, 2^-8 = 3.9e-3)."""
     torch = need_gpu()
-    n = 8
     mg_o = Multigrid(n, k, n_coarse=n)
     S = mg_o.fine["S"]
     x0 = uniform_vector(S.ndof, seed=50 + k)
@@ -37,22 +48,22 @@ def test_direct_sweep_matches_oracle(k):
     b[S.offsets[3]:] -= b[S.offsets[3]:].mean()
     xref = mg_o.smooth(0, x0, b)
     dref = xref - x0
-    mg = _direct_mg(n, k, levels=1)
-    for mode, tol in (("f32", 1e-6), ("bf16", 2e-3)):
-        announce("direct sweep", f"n={n} k={k} mode={mode}")
+    mg = _direct_mg(n, k, levels=1, rows=rows)
+    for mode, tol in (("f32", 1e-6), ("bf16", 2.0 ** -8)):
+        announce("direct sweep", f"n={n} k={k} rows={rows} mode={mode}")
         mg.set_local_solver("direct", mode)
         x = torch.from_numpy(x0).cuda()
         mg.smooth(x, torch.from_numpy(b).cuda())
         e = rel_err(x.cpu().numpy() - x0, dref)
-        print(f"k={k} {mode}: relative error of the sweep's correction {e:.2e}", flush=True)
+        print(f"n={n} k={k} {mode}: relative error of the sweep's correction {e:.2e}", flush=True)
         assert e <= tol, (k, mode, e)
     mg.set_local_solver("exact")
 
 
 def test_direct_solve_converges_like_exact():
-    """FP64 FGMRES with an FP32 V-cycle whose interior local solves are the
-    BF16 Direct GEMM: reaches 1e-8 on 32^3 cells, k = 2, in at most one step
-    more than the exact local solver."""
+    """FP64 FGMRES with an FP32 V-cycle whose local solves are all the Direct
+    GEMM (BF16 or FP32 operands): reaches 1e-8 on 32^3 cells, k = 2, in at
+    most one step more than the exact local solver."""
     torch = need_gpu()
     n, k = 32, 2
     mg = StokesMG(n, k, cg_rtol=1e-3, cg_max_it=15)
@@ -79,3 +90,12 @@ def test_direct_needs_setup():
     mg.mlp_setup(1024)
     with pytest.raises(StokesMGError):
         mg.set_local_solver("direct", "bf16")
+
+
+def test_direct_needs_128_rows():
+    torch = need_gpu()
+    mg = StokesMG(8, 1)
+    from paper_2410_09497_amd import StokesMGError
+    mg.mlp_setup(64)
+    with pytest.raises(StokesMGError):
+        mg.direct_setup()
