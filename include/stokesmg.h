@@ -260,9 +260,10 @@ int stokesmg_rhs_fourier(stokesmg_t* h, int level, int n_modes, const int* kappa
 #define STOKESMG_LOCAL_DIRECT 3  /* the "Direct" solver of Sec. 3.3 on every patch: the patch
                                     pseudo-inverse as one dense matrix per patch type (the same on
                                     every level in the normalized variables of the gather), applied
-                                    to a colour's patches as one grouped GEMM on the matrix cores
-                                    (BF16 or FP32 operands per mlp_mode, FP32 accumulation); no
-                                    local iteration.  Needs stokesmg_direct_setup(). */
+                                    to all patches of a colour in one kernel that gathers the patch
+                                    residuals, multiplies them on the matrix cores (BF16 or FP32
+                                    operands per mlp_mode, FP32 accumulation) and adds the
+                                    corrections; no local iteration.  Needs stokesmg_direct_setup(). */
 
 /* d (network width in and out) and P (parameter count) for the handle's degree. */
 int mlp_dims(const stokesmg_t* h, int64_t* d, int64_t* n_params);
@@ -331,8 +332,7 @@ int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode, dou
  * doubles, row-major [out][in], d from mlp_dims; no device needed; EINVAL
  * for a type outside 0..27).  stokesmg_direct_setup builds all 28 (on host
  * threads) and uploads them (FP32) into the MLP workspace, which must be set
- * (ENOMEM) with at least 128 rows (EINVAL); synchronizes `stream`.  Degrees
- * 1..3 (EUNSUPPORTED). */
+ * (ENOMEM); synchronizes `stream`.  Degrees 1..3 (EUNSUPPORTED). */
 int stokesmg_direct_matrix(const stokesmg_t* h, int type, double* M);
 int stokesmg_direct_setup(stokesmg_t* h, void* stream);
 

@@ -182,24 +182,14 @@ int mlp_interior_solve(stokesmg* h, int level, bool f64, void* x, const void* r,
     return STOKESMG_OK;
 }
 
-// every patch of one colour by the Direct solver: gather, one GEMM per chunk
-// with each patch type's normalized map on the matrix cores (BF16 or FP32
-// operands per the MLP mode, FP32 accumulation), scatter
+// every patch of one colour by the Direct solver: one launch that gathers
+// each patch's residual, multiplies it by its patch type's normalized map on
+// the matrix cores (BF16 or FP32 operands per the MLP mode, FP32
+// accumulation) and adds the correction
 int direct_solve(stokesmg* h, int level, bool f64, void* x, const void* r, int colour, hipStream_t st) {
-    auto& m = h->mlp;
     const int n = h->lv[level].n, k = h->cfg.k;
-    const PatchGroups pg = colour_groups(n, colour, true);
-    const int total = pg.start[pg.ng];
-    const int chunk = int(m.rows / kGroupAlign) * kGroupAlign;
-    const bool bf16 = h->mlp_mode == STOKESMG_MLP_BF16;
-    float *X = at<float>(h, m.X), *Y = at<float>(h, m.Y), *s = at<float>(h, m.s);
-    const float* Mt = at<float>(h, m.direct);
-    for (int r0 = 0; r0 < total; r0 += chunk) {
-        const int cnt = std::min(chunk, total - r0);
-        SMG_HIP(h, launch_group_gather(f64, r, n, k, pg, r0, cnt, X, m.d, s, st));
-        SMG_HIP(h, launch_gemm_grouped(bf16, cnt, m.d, m.d, X, m.d, Mt, m.d, size_t(m.d) * m.d, Y, m.d, pg, r0, st));
-        SMG_HIP(h, launch_group_scatter(f64, x, n, k, pg, r0, cnt, Y, m.d, s, 1.0, st));
-    }
+    SMG_HIP(h, launch_direct_patch(f64, h->mlp_mode == STOKESMG_MLP_BF16, r, x, n, k, colour_groups(n, colour, true),
+                                   at<float>(h, h->mlp.direct), st));
     return STOKESMG_OK;
 }
 
@@ -483,8 +473,6 @@ int stokesmg_direct_setup(stokesmg_t* h, void* stream) {
     if (!h) return STOKESMG_EINVAL;
     if (h->cfg.k > 3) return h->fail(STOKESMG_EUNSUPPORTED, "the Direct solver is built for degrees 1..3");
     if (!h->mlp.ws) return h->fail(STOKESMG_ENOMEM, "no MLP workspace set (it holds the Direct solver's matrices)");
-    if (h->mlp.rows < smg::kGroupAlign)
-        return h->fail(STOKESMG_EINVAL, "the Direct solver needs an MLP workspace of at least 128 rows");
     std::vector<std::vector<double>> D;
     try {
         D = smg::direct_type_maps(smg::Ref1D(h->cfg.k), h->cfg.penalty_factor);

@@ -9,6 +9,7 @@
 // multiplied.  Split-K (deterministic: partial tiles, then a sum) keeps the
 // long-K weight-gradient products from running on a handful of CUs.
 #include "mlp_kernels.hpp"
+#include "xcd.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -50,11 +51,6 @@ struct GemmArgs {
     int ldz;
     int kslabs_per_split;   // k slabs handled by one blockIdx.z
     size_t split_stride;    // floats between the partial C of consecutive splits
-    int ng;                 // > 0: grouped rows; the tile at row m0 uses B + gmat[g] bstride
-    int grow0;              // group-space row of A's row 0
-    int gstart[kMaxGroups + 1];
-    int gmat[kMaxGroups];
-    size_t bstride;
 };
 
 // One operand tile of R rows x GBK k, R = 32 T: thread t fetches 16 elements
@@ -140,14 +136,6 @@ __global__ void __launch_bounds__(GNT) gemm_kernel(GemmArgs g) {
     const int nslab_total = (g.K + GBK - 1) / GBK;
     const int s_begin = blockIdx.z * g.kslabs_per_split;
     const int s_end = min(nslab_total, s_begin + g.kslabs_per_split);
-    const float* Bsrc = g.B;
-    if (g.ng > 0) {
-        // a tile never straddles two groups: groups start at multiples of kGroupAlign, a multiple of BM
-        const int row = g.grow0 + m0;
-        int gi = 0;
-        while (gi + 1 < g.ng && g.gstart[gi + 1] <= row) ++gi;
-        Bsrc += size_t(g.gmat[gi]) * g.bstride;
-    }
 
     // A element (m, k): !TA -> A[row(m) lda + k] (k contiguous); TA -> A[row(k) lda + m]
     TileLoader<BM, !TA> la;
@@ -162,7 +150,7 @@ __global__ void __launch_bounds__(GNT) gemm_kernel(GemmArgs g) {
 
     if (s_begin < s_end) {
         la.load(g.A, g.lda, g.arows, m0, g.M, s_begin * GBK, g.K, t);
-        lb.load(Bsrc, g.ldb, nullptr, n0, g.N, s_begin * GBK, g.K, t);
+        lb.load(g.B, g.ldb, nullptr, n0, g.N, s_begin * GBK, g.K, t);
     }
     const int fr = lane & 15, fq = lane >> 4;
     for (int s = s_begin; s < s_end; ++s) {
@@ -172,7 +160,7 @@ __global__ void __launch_bounds__(GNT) gemm_kernel(GemmArgs g) {
         __syncthreads();
         if (s + 1 < s_end) {
             la.load(g.A, g.lda, g.arows, m0, g.M, (s + 1) * GBK, g.K, t);
-            lb.load(Bsrc, g.ldb, nullptr, n0, g.N, (s + 1) * GBK, g.K, t);
+            lb.load(g.B, g.ldb, nullptr, n0, g.N, (s + 1) * GBK, g.K, t);
         }
         if constexpr (sizeof(TOP) == 2) {
             bf16x8 a[TI], b[TJ];
@@ -300,27 +288,6 @@ hipError_t launch_gemm(bool bf16, Epi epi, bool ta, bool tb, int M, int N, int K
     hipLaunchKernelGGL(split_sum_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, split_ws, splits,
                        g.split_stride, M, N, ldc, C);
     return hipGetLastError();
-}
-
-hipError_t launch_gemm_grouped(bool bf16, int rows, int N, int K, const float* A, int lda, const float* B, int ldb,
-                               size_t bstride, float* C, int ldc, const PatchGroups& pg, int row0, hipStream_t st) {
-    if (rows <= 0 || N <= 0 || pg.ng <= 0) return hipSuccess;
-    if (row0 % kGroupAlign != 0) return hipErrorInvalidValue;
-    GemmArgs g{rows, N, K, A, lda, nullptr, B, ldb, C, ldc, nullptr, nullptr, 0, 0, 0};
-    g.kslabs_per_split = std::max(1, (K + GBK - 1) / GBK);
-    g.ng = pg.ng;
-    g.grow0 = row0;
-    for (int i = 0; i <= pg.ng; ++i) g.gstart[i] = pg.start[i];
-    for (int i = 0; i < pg.ng; ++i) g.gmat[i] = pg.mat[i];
-    g.bstride = bstride;
-    static_assert(kGroupAlign % 128 == 0, "a row tile must not straddle two groups");
-    const bool big = size_t((rows + 127) / 128) * ((N + 127) / 128) >= 512;
-    const int bt = big ? 128 : 64;
-    const dim3 grid((N + bt - 1) / bt, (rows + bt - 1) / bt, 1);
-    if (big) return bf16 ? gemm_dispatch_t<__bf16, 4, 4, Epi::Store>(false, false, g, grid, st)
-                         : gemm_dispatch_t<float, 4, 4, Epi::Store>(false, false, g, grid, st);
-    return bf16 ? gemm_dispatch_t<__bf16, 2, 2, Epi::Store>(false, false, g, grid, st)
-                : gemm_dispatch_t<float, 2, 2, Epi::Store>(false, false, g, grid, st);
 }
 
 // ---------------------------------------------------------------- loss, sums, Adam
@@ -597,6 +564,8 @@ __global__ void __launch_bounds__(256) patch_gather_diff_kernel(const T* __restr
 
 }  // namespace
 
+namespace {
+
 hipError_t launch_group_gather(bool f64, const void* r, int n, int k, const PatchGroups& pg, int r0, int rows,
                                float* X, int ldx, float* s, hipStream_t st) {
     if (rows <= 0 || pg.ng <= 0) return hipSuccess;
@@ -618,6 +587,8 @@ hipError_t launch_group_scatter(bool f64, void* x, int n, int k, const PatchGrou
                             r0, Y, ldy, s, omega);
     return hipGetLastError();
 }
+
+}  // namespace
 
 hipError_t launch_patch_gather(bool f64, const void* r, int n, int k, int colour, int p0, int np, float* X, int ldx,
                                float* s, hipStream_t st) {
@@ -641,6 +612,222 @@ hipError_t launch_patch_gather_diff(bool f64, const void* xnew, const void* xold
     else hipLaunchKernelGGL(patch_gather_diff_kernel<float>, dim3(np), dim3(256), 0, st,
                             static_cast<const float*>(xnew), static_cast<const float*>(xold), g, pg, p0, T, ldt, s);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- Direct solver: gather, GEMM, scatter fused
+
+namespace {
+
+// Patch-local entry q -> offset from its component's corner of the patch: the
+// index of entry q in the level vector is base[comp(q)] + offset(q)
+__device__ inline int local_offset(const PatchGeo& g, int q) {
+    if (q < 3 * g.nvel) {
+        const int c = q / g.nvel, w = q - c * g.nvel;
+        const int l0 = c == 0 ? g.lc : g.m, l1 = c == 1 ? g.lc : g.m;
+        const int i0 = w % l0, i1 = (w / l0) % l1, i2 = w / (l0 * l1);
+        const int e0 = c == 0 ? g.N1 - 1 : g.N1, e1 = c == 1 ? g.N1 - 1 : g.N1;
+        return i0 + e0 * (i1 + e1 * i2);
+    }
+    const int w = q - 3 * g.nvel;
+    const int i0 = w % g.m, i1 = (w / g.m) % g.m, i2 = w / (g.m * g.m);
+    return i0 + g.N1 * (i1 + g.N1 * i2);
+}
+
+__device__ inline int comp_of(const PatchGeo& g, int q) {
+    return (q >= g.nvel) + (q >= 2 * g.nvel) + (q >= 3 * g.nvel);
+}
+
+struct DirectArgs {
+    const void* r;     // residual (level vector)
+    void* x;           // iterate (level vector), x += the patch corrections
+    const float* B;    // kDirectTypes matrices, each d x d row-major [in][out]
+    size_t bstride;
+    int rows, d;       // grouped row space of the colour, patch dimension
+    PatchGeo geo;
+    PatchGroups pg;
+};
+
+constexpr int kMaxPatchDim = 3 * 7 * 8 * 8 + 8 * 8 * 8;   // k = 3
+
+// One (BM x BN) tile of Y = X M_type for the rows of a colour's grouped row
+// space, where row i of X is the normalized residual of patch i,
+// (r_vel / h, r_pres / h^2), read straight from the level vector, and row i
+// of Y its normalized correction (U, h P), added straight into x.  The GEMM
+// part is gemm_kernel's (same LDS layout and MFMA fragments); the A tile is
+// gathered from r instead of a row buffer and the epilogue scatters.  Within
+// a colour the patches are disjoint, so every x entry is updated by exactly
+// one lane of one workgroup.  One-dimensional grid of row tiles x column
+// tiles, ordered so that the column tiles of a row tile share an XCD (and its
+// L2 copy of the row tile's residual entries).
+template <typename TOP, typename T, int TI, int TJ>
+__global__ void __launch_bounds__(GNT) direct_patch_kernel(DirectArgs a) {
+    constexpr int BM = 32 * TI, BN = 32 * TJ, LD = GBK + Op<TOP>::PAD;
+    constexpr int PER = BM * GBK / GNT, TPR = GBK / PER;
+    __shared__ __attribute__((aligned(16))) TOP As[BM * LD];
+    __shared__ __attribute__((aligned(16))) TOP Bs[BN * LD];
+    __shared__ int off[kMaxPatchDim];
+    __shared__ long long rbase[BM][4];
+
+    const PatchGeo& g = a.geo;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int ntn = (a.d + BN - 1) / BN;
+    const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int m0 = (tile / ntn) * BM, n0 = (tile % ntn) * BN;
+
+    // tables of this tile: entry offsets, and each row's component corners (-1: padding row)
+    for (int q = t; q < a.d; q += GNT) off[q] = local_offset(g, q);
+    for (int rr = t; rr < BM; rr += GNT) {
+        int v[3];
+        if (m0 + rr < a.rows && group_vertex(a.pg, m0 + rr, v)) {
+            const long long b0 = (v[0] - 1) * (g.k + 1), b1 = (v[1] - 1) * (g.k + 1), b2 = (v[2] - 1) * (g.k + 1);
+            const long long N1 = g.N1;
+            rbase[rr][0] = b0 + (N1 - 1) * (b1 + N1 * b2);
+            rbase[rr][1] = (long long)g.nc + b0 + N1 * (b1 + (N1 - 1) * b2);
+            rbase[rr][2] = 2 * (long long)g.nc + b0 + N1 * (b1 + N1 * b2);
+            rbase[rr][3] = 3 * (long long)g.nc + b0 + N1 * (b1 + N1 * b2);
+        } else {
+            rbase[rr][0] = -1;
+        }
+    }
+    const float* Bsrc = a.B;
+    {
+        int gi = 0;
+        while (gi + 1 < a.pg.ng && a.pg.start[gi + 1] <= m0) ++gi;
+        Bsrc += size_t(a.pg.mat[gi]) * a.bstride;
+    }
+    __syncthreads();
+
+    // A loader: thread t gathers PER consecutive entries of row ar
+    const int ar = t / TPR, akk = (t % TPR) * PER;
+    long long ab[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ab[c] = rbase[ar][c];
+    const T* __restrict__ r = static_cast<const T*>(a.r);
+    const float sv = float(g.n), sp = float(g.n) * float(g.n);   // 1/h and 1/h^2, powers of two
+    float av[PER];
+    auto load_a = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = k0 + akk + i;
+            float val = 0.0f;
+            if (ab[0] >= 0 && q < a.d) {
+                const int c = comp_of(g, q);
+                val = float(r[ab[c] + off[q]]) * (c == 3 ? sp : sv);
+            }
+            av[i] = val;
+        }
+    };
+    auto store_a = [&]() {
+        TOP* dst = As + ar * LD + akk;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) dst[i] = TOP(av[i]);
+    };
+    TileLoader<BN, false> lb;
+
+    f32x4 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const int nslab = (a.d + GBK - 1) / GBK;
+    load_a(0);
+    lb.load(Bsrc, a.d, nullptr, n0, a.d, 0, a.d, t);
+    const int fr = lane & 15, fq = lane >> 4;
+    for (int s = 0; s < nslab; ++s) {
+        __syncthreads();   // previous slab fully consumed
+        store_a();
+        lb.store(Bs, t);
+        __syncthreads();
+        if (s + 1 < nslab) {
+            load_a((s + 1) * GBK);
+            lb.load(Bsrc, a.d, nullptr, n0, a.d, (s + 1) * GBK, a.d, t);
+        }
+        if constexpr (sizeof(TOP) == 2) {
+            bf16x8 af[TI], bf[TJ];
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+                af[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * 16 * TI + i * 16 + fr) * LD + fq * 8]);
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+                bf[j] = *reinterpret_cast<const bf16x8*>(&Bs[(wn * 16 * TJ + j * 16 + fr) * LD + fq * 8]);
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < GBK / 4; ++q) {
+                float af[TI], bf[TJ];
+#pragma unroll
+                for (int i = 0; i < TI; ++i) af[i] = As[(wm * 16 * TI + i * 16 + fr) * LD + 4 * q + fq];
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) bf[j] = Bs[(wn * 16 * TJ + j * 16 + fr) * LD + 4 * q + fq];
+#pragma unroll
+                for (int i = 0; i < TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+
+    // x[entry] += Y[row][col] (velocity) or Y[row][col] / h (pressure);
+    // Y[row][col]: row = tile row + 4 (lane / 16) + e, col = tile col + lane % 16
+    T* __restrict__ x = static_cast<T*>(a.x);
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+        const int col = n0 + wn * 16 * TJ + j * 16 + fr;
+        if (col >= a.d) continue;
+        const int c = comp_of(g, col), o = off[col];
+        const float sc = c == 3 ? sv : 1.0f;
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rl = wm * 16 * TI + i * 16 + 4 * fq + e;
+                if (rbase[rl][0] < 0) continue;
+                T* p = x + rbase[rl][c] + o;
+                *p = T(*p + T(acc[i][j][e] * sc));
+            }
+    }
+}
+
+template <typename TOP, typename T, int TI>
+hipError_t direct_dispatch(const DirectArgs& a, hipStream_t st) {
+    constexpr int BT = 32 * TI;
+    const int tiles = ((a.rows + BT - 1) / BT) * ((a.d + BT - 1) / BT);
+    hipLaunchKernelGGL((direct_patch_kernel<TOP, T, TI, TI>), dim3(tiles), dim3(GNT), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_direct_patch(bool f64, bool bf16, const void* r, void* x, int n, int k, const PatchGroups& pg,
+                               const float* B, hipStream_t st) {
+    const int rows = pg.ng > 0 ? pg.start[pg.ng] : 0;
+    if (rows <= 0) return hipSuccess;
+    DirectArgs a;
+    a.r = r;
+    a.x = x;
+    a.B = B;
+    a.geo = make_geo(n, k);
+    a.d = a.geo.size;
+    a.bstride = size_t(a.d) * a.d;
+    a.rows = rows;
+    a.pg = pg;
+    if (a.d > kMaxPatchDim) return hipErrorInvalidValue;
+    static_assert(kGroupAlign % 128 == 0, "a row tile must not straddle two groups");
+    // 128 x 128 tiles when they still give two workgroups per CU, else 64 x 64
+    const bool big = size_t((rows + 127) / 128) * ((a.d + 127) / 128) >= 512;
+    if (big) {
+        if (bf16) return f64 ? direct_dispatch<__bf16, double, 4>(a, st) : direct_dispatch<__bf16, float, 4>(a, st);
+        return f64 ? direct_dispatch<float, double, 4>(a, st) : direct_dispatch<float, float, 4>(a, st);
+    }
+    if (bf16) return f64 ? direct_dispatch<__bf16, double, 2>(a, st) : direct_dispatch<__bf16, float, 2>(a, st);
+    return f64 ? direct_dispatch<float, double, 2>(a, st) : direct_dispatch<float, float, 2>(a, st);
 }
 
 // ---------------------------------------------------------------- training helpers

@@ -57,7 +57,7 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, f
 // 0: neither; 27: the single patch of n = 2).  all_types = false: the interior
 // patches only, one group from row 0 (rows p0 .. of the interior launchers).
 // all_types = true: every patch of the colour, each group padded to a
-// multiple of kGroupAlign rows (padding rows gather as zero with s = 0).
+// multiple of kGroupAlign rows (padding rows belong to no patch).
 constexpr int kMaxGroups = 27;
 constexpr int kGroupAlign = 128;
 struct PatchGroups {
@@ -69,18 +69,14 @@ struct PatchGroups {
 };
 PatchGroups colour_groups(int n, int colour, bool all_types);
 
-// C[rows x N] = A B_g for the rows of a grouped row space (colour_groups with
-// all_types): A's row i is row row0 + i of that space (row0 a multiple of
-// kGroupAlign) and uses B_g = B + mat[g] bstride, K x N row-major.  Epi::Store.
-hipError_t launch_gemm_grouped(bool bf16, int rows, int N, int K, const float* A, int lda, const float* B, int ldb,
-                               size_t bstride, float* C, int ldc, const PatchGroups& pg, int row0, hipStream_t st);
-
-// Rows r0 .. r0+rows-1 of a grouped row space, patch-local vectors of a level
-// vector (row q of X / Y belongs to row r0 + q); the same scaling as below.
-hipError_t launch_group_gather(bool f64, const void* r, int n, int k, const PatchGroups& pg, int r0, int rows,
-                               float* X, int ldx, float* s, hipStream_t st);
-hipError_t launch_group_scatter(bool f64, void* x, int n, int k, const PatchGroups& pg, int r0, int rows,
-                                const float* Y, int ldy, const float* s, double omega, hipStream_t st);
+// The Direct solver on every patch of one colour (colour_groups with
+// all_types), in one launch: x[R_j] += M_type (R_j r scaled by 1/h (velocity)
+// and 1/h^2 (pressure)), the output's pressure rows scaled by 1/h, for each
+// patch j; M_type = B + mat[g] d^2, d x d row-major [in][out] FP32.  Products
+// on the matrix cores with BF16 (bf16) or FP32 operands and FP32
+// accumulation.  r and x: level vectors (double if f64, else float), distinct.
+hipError_t launch_direct_patch(bool f64, bool bf16, const void* r, void* x, int n, int k, const PatchGroups& pg,
+                               const float* B, hipStream_t st);
 
 // Interior patches p0 .. p0+np-1 of one colour: patch-local vectors of a
 // level vector (row q of X / Y / T belongs to patch p0 + q).

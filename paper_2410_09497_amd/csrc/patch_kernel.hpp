@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "patch_tables.hpp"
+#include "xcd.hpp"
 
 namespace smg {
 
@@ -254,12 +255,6 @@ struct PatchIndex {
     }
 };
 
-__device__ inline int patch_xcd_remap(int bid, int G) {
-    const int xcd = bid & 7, local = bid >> 3;
-    const int per = G >> 3, extra = G & 7;
-    return xcd * per + (xcd < extra ? xcd : extra) + local;
-}
-
 // Warm start of the Schur CG (interior patches only): the patch pressure
 // predicted by the network, normalized as in its training pairs --
 // row b of y holds (U, h P) / s for the interior patch p0 + b of the colour,
@@ -292,7 +287,7 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     // that each XCD gets a contiguous eighth of the colour's patches.  With the plain order the
     // boundary-only launches put every x-boundary patch (first and last of each row of 64 patches)
     // on two XCDs and ran about 10x longer.
-    const int b = patch_xcd_remap(blockIdx.x, gridDim.x);
+    const int b = xcd_contiguous(blockIdx.x, gridDim.x);
     const bool warm_start = warm.y != nullptr;
     int vx, vy, vz;
     if (warm_start) {

@@ -1,6 +1,7 @@
 """The Direct local solver (Sec. 3.3) on the matrix cores: every patch of a
-colour by one grouped GEMM per chunk with the normalized pseudo-inverse of
-its patch type (interior, face, edge, corner; the single patch of n = 2).
+colour in one launch that gathers the patch residuals, multiplies them by
+the normalized pseudo-inverse of their patch type (interior, face, edge,
+corner; the single patch of n = 2) and scatters the corrections.
 Against the oracle's smoother with pseudo-inverse local solves on every
 patch, and inside the mixed-precision solve."""
 import numpy as np
@@ -14,24 +15,22 @@ from paper_2410_09497_amd.synth import uniform_vector
 pytestmark = pytest.mark.gpu
 
 
-def _direct_mg(n, k, levels=None, cg_rtol=1e-12, cg_max_it=300, rows=4096):
+def _direct_mg(n, k, levels=None, cg_rtol=1e-12, cg_max_it=300):
     mg = StokesMG(n, k, n_levels=levels, cg_rtol=cg_rtol, cg_max_it=cg_max_it)
-    mg.mlp_setup(rows)
+    mg.mlp_setup(1024)
     mg.direct_setup()
     return mg
 
 
-CASES = [(8, 1, 4096), (8, 2, 4096), (8, 3, 4096),
-         # chunks of 128 rows: every group (padded to 128 rows) in a chunk of its own
-         (8, 1, 128),
+CASES = [(8, 1), (8, 2), (8, 3),
          # n = 4: every patch touches the boundary (all 27 types, vertices 1..3)
-         (4, 2, 4096),
+         (4, 2),
          # n = 2: the single patch, boundary on all six outer faces
-         (2, 1, 4096), (2, 2, 4096)]
+         (2, 1), (2, 2)]
 
 
-@pytest.mark.parametrize("n,k,rows", CASES)
-def test_direct_sweep_matches_oracle(n, k, rows):
+@pytest.mark.parametrize("n,k", CASES)
+def test_direct_sweep_matches_oracle(n, k):
     """One sweep.  The GEMM rounds the normalized residuals and the matrix to
     its operand precision and accumulates in FP32; every patch of the sweep
     goes through it.  Each product term carries at most one rounding of
@@ -48,14 +47,41 @@ def test_direct_sweep_matches_oracle(n, k, rows):
     b[S.offsets[3]:] -= b[S.offsets[3]:].mean()
     xref = mg_o.smooth(0, x0, b)
     dref = xref - x0
-    mg = _direct_mg(n, k, levels=1, rows=rows)
+    mg = _direct_mg(n, k, levels=1)
     for mode, tol in (("f32", 1e-6), ("bf16", 2.0 ** -8)):
-        announce("direct sweep", f"n={n} k={k} rows={rows} mode={mode}")
+        announce("direct sweep", f"n={n} k={k} mode={mode}")
         mg.set_local_solver("direct", mode)
         x = torch.from_numpy(x0).cuda()
         mg.smooth(x, torch.from_numpy(b).cuda())
         e = rel_err(x.cpu().numpy() - x0, dref)
         print(f"n={n} k={k} {mode}: relative error of the sweep's correction {e:.2e}", flush=True)
+        assert e <= tol, (k, mode, e)
+    mg.set_local_solver("exact")
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_direct_sweep_full_size_matches_exact_sweep(k):
+    """64^3 cells, where the kernel runs 128 x 128 tiles (the 8^3 cases run
+    64 x 64): one Direct sweep against one sweep of the exact local solver
+    (FP64 Schur CG to 1e-12, itself checked against the oracle at small
+    sizes), same seeded inputs, same bounds as above."""
+    torch = need_gpu()
+    n = 64
+    mg = _direct_mg(n, k, levels=1)
+    N = mg.ndof()
+    x0 = torch.from_numpy(uniform_vector(N, seed=70 + k)).cuda()
+    b = torch.from_numpy(uniform_vector(N, seed=80 + k)).cuda()
+    announce("direct sweep vs exact", f"n={n} k={k}")
+    mg.set_local_solver("exact")
+    xe = x0.clone()
+    mg.smooth(xe, b)
+    de = (xe - x0).cpu().numpy()
+    for mode, tol in (("f32", 1e-6), ("bf16", 2.0 ** -8)):
+        mg.set_local_solver("direct", mode)
+        x = x0.clone()
+        mg.smooth(x, b)
+        e = rel_err((x - x0).cpu().numpy(), de)
+        print(f"n={n} k={k} {mode}: relative difference to the exact sweep {e:.2e}", flush=True)
         assert e <= tol, (k, mode, e)
     mg.set_local_solver("exact")
 
@@ -90,12 +116,3 @@ def test_direct_needs_setup():
     mg.mlp_setup(1024)
     with pytest.raises(StokesMGError):
         mg.set_local_solver("direct", "bf16")
-
-
-def test_direct_needs_128_rows():
-    torch = need_gpu()
-    mg = StokesMG(8, 1)
-    from paper_2410_09497_amd import StokesMGError
-    mg.mlp_setup(64)
-    with pytest.raises(StokesMGError):
-        mg.direct_setup()
