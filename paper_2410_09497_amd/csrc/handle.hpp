@@ -54,7 +54,7 @@ struct stokesmg {
         int d = 0, H = 256;
         int64_t P = 0;             // parameter count
         size_t params, grads, m, v, Z1, H1, Z2, H2, Y, dY, dZ2, dZ1, X, s, split, lossp, loss, colp, brows, acc;
-        size_t direct = 0;         // the Direct solver's normalized interior map, d x d FP32 [in][out]
+        size_t direct = 0;         // the Direct solver's maps per patch type, padded [out][in]: FP32, then BF16
         bool direct_ready = false; // stokesmg_direct_setup() has filled it
         size_t split_floats = 0;
         int64_t step = 0;          // Adam steps taken

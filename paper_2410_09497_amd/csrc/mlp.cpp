@@ -56,8 +56,10 @@ size_t layout(stokesmg::Mlp& m, int d, int H, int64_t R) {
     put(m.colp, size_t(smg::kColsumSplit) * (d > H ? d : H) * f);
     put(m.brows, R * sizeof(int));
     put(m.acc, sizeof(double));
-    // the Direct solver's matrices, one per patch type (degrees 1..3 only)
-    put(m.direct, d <= patch_dim(3) ? size_t(smg::kDirectTypes) * d * d * f : 0);
+    // the Direct solver's matrices, one per patch type, FP32 then BF16 (degrees 1..3 only)
+    int dk = 0, dn = 0;
+    smg::direct_dims(d, &dk, &dn);
+    put(m.direct, d <= patch_dim(3) ? size_t(smg::kDirectTypes) * dn * dk * (f + 2) : 0);
     return off;
 }
 
@@ -188,8 +190,12 @@ int mlp_interior_solve(stokesmg* h, int level, bool f64, void* x, const void* r,
 // accumulation) and adds the correction
 int direct_solve(stokesmg* h, int level, bool f64, void* x, const void* r, int colour, hipStream_t st) {
     const int n = h->lv[level].n, k = h->cfg.k;
-    SMG_HIP(h, launch_direct_patch(f64, h->mlp_mode == STOKESMG_MLP_BF16, r, x, n, k, colour_groups(n, colour, true),
-                                   at<float>(h, h->mlp.direct), st));
+    const bool bf16 = h->mlp_mode == STOKESMG_MLP_BF16;
+    int dk = 0, dn = 0;
+    direct_dims(h->mlp.d, &dk, &dn);
+    const size_t f32_bytes = size_t(kDirectTypes) * dn * dk * sizeof(float);
+    const void* Bt = h->mlp.ws + h->mlp.direct + (bf16 ? f32_bytes : 0);
+    SMG_HIP(h, launch_direct_patch(f64, bf16, r, x, n, k, colour_groups(n, colour, true), Bt, st));
     return STOKESMG_OK;
 }
 
@@ -480,13 +486,25 @@ int stokesmg_direct_setup(stokesmg_t* h, void* stream) {
         return h->fail(STOKESMG_EINVAL, e.what());
     }
     const int d = h->mlp.d;
-    const size_t dd = size_t(d) * d;
-    std::vector<float> Mt(smg::kDirectTypes * dd);   // per type [in][out], the B operand of the GEMM
+    int dk = 0, dn = 0;
+    smg::direct_dims(d, &dk, &dn);
+    const size_t per = size_t(dn) * dk, total = smg::kDirectTypes * per;
+    // per type M padded with zeros to dn x dk, [out][in]: FP32, then the same rounded to BF16 (nearest even)
+    std::vector<float> Mf(total, 0.0f);
+    std::vector<uint16_t> Mb(total, 0);
     for (int t = 0; t < smg::kDirectTypes; ++t)
         for (int o = 0; o < d; ++o)
-            for (int i = 0; i < d; ++i) Mt[t * dd + size_t(i) * d + o] = float(D[t][size_t(o) * d + i]);
+            for (int i = 0; i < d; ++i) {
+                const float v = float(D[t][size_t(o) * d + i]);
+                uint32_t u;
+                std::memcpy(&u, &v, 4);
+                Mf[t * per + size_t(o) * dk + i] = v;
+                Mb[t * per + size_t(o) * dk + i] = uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+            }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    SMG_HIP(h, hipMemcpyAsync(h->mlp.ws + h->mlp.direct, Mt.data(), Mt.size() * sizeof(float), hipMemcpyHostToDevice,
+    char* dst = h->mlp.ws + h->mlp.direct;
+    SMG_HIP(h, hipMemcpyAsync(dst, Mf.data(), total * sizeof(float), hipMemcpyHostToDevice, st));
+    SMG_HIP(h, hipMemcpyAsync(dst + total * sizeof(float), Mb.data(), total * sizeof(uint16_t), hipMemcpyHostToDevice,
                               st));
     SMG_HIP(h, hipStreamSynchronize(st));
     h->mlp.direct_ready = true;

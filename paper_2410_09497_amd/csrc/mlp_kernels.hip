@@ -616,6 +616,12 @@ hipError_t launch_patch_gather_diff(bool f64, const void* xnew, const void* xold
 
 // ---------------------------------------------------------------- Direct solver: gather, GEMM, scatter fused
 
+void direct_dims(int d, int* dk, int* dn) {
+    const int cols = d <= 256 ? 256 : 384;   // columns of one workgroup: 4 waves x (4 or 6) blocks of 16
+    *dk = (d + 63) / 64 * 64;
+    *dn = (d + cols - 1) / cols * cols;
+}
+
 namespace {
 
 // Patch-local entry q -> offset from its component's corner of the patch: the
@@ -640,194 +646,222 @@ __device__ inline int comp_of(const PatchGeo& g, int q) {
 struct DirectArgs {
     const void* r;     // residual (level vector)
     void* x;           // iterate (level vector), x += the patch corrections
-    const float* B;    // kDirectTypes matrices, each d x d row-major [in][out]
-    size_t bstride;
-    int rows, d;       // grouped row space of the colour, patch dimension
+    const void* Bt;    // per type: M padded to dn x dk, row-major [out][in] (k contiguous), BF16 or FP32
+    size_t bstride;    // elements between two types' matrices (dn dk)
+    int rows, d, dk;   // grouped row space of the colour, patch dimension, padded k extent
     PatchGeo geo;
     PatchGroups pg;
 };
 
-constexpr int kMaxPatchDim = 3 * 7 * 8 * 8 + 8 * 8 * 8;   // k = 3
+constexpr int kMaxPatchDk = 1856;   // k = 3: d = 3 * 7 * 64 + 512, a multiple of 64
+constexpr int DBM = 64, DKC = 64, DPAD = 8;
 
-// One (BM x BN) tile of Y = X M_type for the rows of a colour's grouped row
-// space, where row i of X is the normalized residual of patch i,
-// (r_vel / h, r_pres / h^2), read straight from the level vector, and row i
-// of Y its normalized correction (U, h P), added straight into x.  The GEMM
-// part is gemm_kernel's (same LDS layout and MFMA fragments); the A tile is
-// gathered from r instead of a row buffer and the epilogue scatters.  Within
-// a colour the patches are disjoint, so every x entry is updated by exactly
-// one lane of one workgroup.  One-dimensional grid of row tiles x column
-// tiles, ordered so that the column tiles of a row tile share an XCD (and its
-// L2 copy of the row tile's residual entries).
-template <typename TOP, typename T, int TI, int TJ>
-__global__ void __launch_bounds__(GNT) direct_patch_kernel(DirectArgs a) {
-    constexpr int BM = 32 * TI, BN = 32 * TJ, LD = GBK + Op<TOP>::PAD;
-    constexpr int PER = BM * GBK / GNT, TPR = GBK / PER;
-    __shared__ __attribute__((aligned(16))) TOP As[BM * LD];
-    __shared__ __attribute__((aligned(16))) TOP Bs[BN * LD];
-    __shared__ int off[kMaxPatchDim];
-    __shared__ long long rbase[BM][4];
+template <typename TOP> struct Frag;
+template <> struct Frag<__bf16> {
+    typedef __bf16 v __attribute__((ext_vector_type(8)));
+};
+template <> struct Frag<float> {
+    typedef float v __attribute__((ext_vector_type(8)));
+};
+
+// One workgroup (4 waves) owns 64 patch rows of a colour's grouped row space
+// and 4 x CB x 16 output columns; each wave all 64 rows and CB column blocks.
+// Row i of the product is the normalized residual of patch i,
+// (r_vel / h, r_pres / h^2), gathered from the level vector; the product with
+// the patch type's map M (the row tile's group) is added into x as (U, h P)
+// -> velocity U, pressure (h P) / h.  The k range runs in chunks of 64: a
+// chunk of the gathered rows sits in LDS (double buffered: the next chunk's
+// loads are in flight during this chunk's products); the M fragments come
+// straight from global memory (L2), one k-step ahead.  A lane's fragments
+// cover 8 consecutive k of a 32-wide k-step: one 16x16x32 BF16 MFMA, or
+// eight 16x16x4 FP32 MFMAs taking the 8 k one at a time (the same k order
+// on both operands).  Within a colour the patches are disjoint, so every x
+// entry has exactly one writer.  Column tiles of a row tile run on one XCD.
+template <typename TOP, typename T, int CB>
+__global__ void __launch_bounds__(256) direct_patch_kernel(DirectArgs a) {
+    constexpr int BN = 4 * CB * 16, LDA = DKC + DPAD;
+    typedef typename Frag<TOP>::v fragv;
+    __shared__ __attribute__((aligned(32))) TOP As[2][DBM * LDA];
+    __shared__ int off[kMaxPatchDk];
+    __shared__ long long rbase[DBM][4];
 
     const PatchGeo& g = a.geo;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wm = w & 1, wn = w >> 1;
+    const int fr = lane & 15, fq = lane >> 4;
     const int ntn = (a.d + BN - 1) / BN;
     const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int m0 = (tile / ntn) * BM, n0 = (tile % ntn) * BN;
+    const int m0 = (tile / ntn) * DBM, n0 = (tile % ntn) * BN;
 
-    // tables of this tile: entry offsets, and each row's component corners (-1: padding row)
-    for (int q = t; q < a.d; q += GNT) off[q] = local_offset(g, q);
-    for (int rr = t; rr < BM; rr += GNT) {
+    for (int q = t; q < a.dk; q += 256) off[q] = q < a.d ? local_offset(g, q) : 0;
+    if (t < DBM) {
         int v[3];
-        if (m0 + rr < a.rows && group_vertex(a.pg, m0 + rr, v)) {
+        if (m0 + t < a.rows && group_vertex(a.pg, m0 + t, v)) {
             const long long b0 = (v[0] - 1) * (g.k + 1), b1 = (v[1] - 1) * (g.k + 1), b2 = (v[2] - 1) * (g.k + 1);
             const long long N1 = g.N1;
-            rbase[rr][0] = b0 + (N1 - 1) * (b1 + N1 * b2);
-            rbase[rr][1] = (long long)g.nc + b0 + N1 * (b1 + (N1 - 1) * b2);
-            rbase[rr][2] = 2 * (long long)g.nc + b0 + N1 * (b1 + N1 * b2);
-            rbase[rr][3] = 3 * (long long)g.nc + b0 + N1 * (b1 + N1 * b2);
+            rbase[t][0] = b0 + (N1 - 1) * (b1 + N1 * b2);
+            rbase[t][1] = (long long)g.nc + b0 + N1 * (b1 + (N1 - 1) * b2);
+            rbase[t][2] = 2 * (long long)g.nc + b0 + N1 * (b1 + N1 * b2);
+            rbase[t][3] = 3 * (long long)g.nc + b0 + N1 * (b1 + N1 * b2);
         } else {
-            rbase[rr][0] = -1;
+            rbase[t][0] = rbase[t][1] = rbase[t][2] = rbase[t][3] = -1;
         }
     }
-    const float* Bsrc = a.B;
+    const TOP* Bt = static_cast<const TOP*>(a.Bt);
     {
-        int gi = 0;
+        int gi = 0;   // the row tile lies in one group: groups start at multiples of 128
         while (gi + 1 < a.pg.ng && a.pg.start[gi + 1] <= m0) ++gi;
-        Bsrc += size_t(a.pg.mat[gi]) * a.bstride;
+        Bt += size_t(a.pg.mat[gi]) * a.bstride;
     }
     __syncthreads();
 
-    // A loader: thread t gathers PER consecutive entries of row ar
-    const int ar = t / TPR, akk = (t % TPR) * PER;
-    long long ab[4];
+    // gather: thread t loads row gr = t mod 64 at k = k0 + w + 4 i (i < 16), wave-uniform k
+    const int gr = t & 63;
+    long long rb[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) ab[c] = rbase[ar][c];
+    for (int c = 0; c < 4; ++c) rb[c] = rbase[gr][c];
+    const bool rvalid = rb[0] >= 0;
     const T* __restrict__ r = static_cast<const T*>(a.r);
     const float sv = float(g.n), sp = float(g.n) * float(g.n);   // 1/h and 1/h^2, powers of two
-    float av[PER];
-    auto load_a = [&](int k0) {
+    float gv[DKC / 4];
+    auto gather_load = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int q = k0 + akk + i;
+        for (int i = 0; i < DKC / 4; ++i) {
+            const int q = k0 + w + 4 * i;
             float val = 0.0f;
-            if (ab[0] >= 0 && q < a.d) {
+            if (rvalid && q < a.d) {
                 const int c = comp_of(g, q);
-                val = float(r[ab[c] + off[q]]) * (c == 3 ? sp : sv);
+                val = float(r[rb[c] + off[q]]) * (c == 3 ? sp : sv);
             }
-            av[i] = val;
+            gv[i] = val;
         }
     };
-    auto store_a = [&]() {
-        TOP* dst = As + ar * LD + akk;
+    auto gather_store = [&](int buf) {
+        TOP* dst = As[buf] + gr * LDA + w;
 #pragma unroll
-        for (int i = 0; i < PER; ++i) dst[i] = TOP(av[i]);
+        for (int i = 0; i < DKC / 4; ++i) dst[4 * i] = TOP(gv[i]);
     };
-    TileLoader<BN, false> lb;
 
-    f32x4 acc[TI][TJ];
+    // M fragments: lane (fr, fq) of column block j reads M[col][k .. k + 7], col = n0 + (w CB + j) 16 + fr
+    const TOP* bp[CB];
 #pragma unroll
-    for (int i = 0; i < TI; ++i)
+    for (int j = 0; j < CB; ++j) bp[j] = Bt + size_t(n0 + (w * CB + j) * 16 + fr) * a.dk + fq * 8;
+    fragv bcur[CB], bnext[CB];
+    auto b_load = [&](fragv* dst, int k) {
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int j = 0; j < CB; ++j) dst[j] = *reinterpret_cast<const fragv*>(bp[j] + k);
+    };
 
-    const int nslab = (a.d + GBK - 1) / GBK;
-    load_a(0);
-    lb.load(Bsrc, a.d, nullptr, n0, a.d, 0, a.d, t);
-    const int fr = lane & 15, fq = lane >> 4;
-    for (int s = 0; s < nslab; ++s) {
-        __syncthreads();   // previous slab fully consumed
-        store_a();
-        lb.store(Bs, t);
-        __syncthreads();
-        if (s + 1 < nslab) {
-            load_a((s + 1) * GBK);
-            lb.load(Bsrc, a.d, nullptr, n0, a.d, (s + 1) * GBK, a.d, t);
-        }
+    f32x4 acc[4][CB];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const int nchunk = a.dk / DKC, nstep = a.dk / 32;
+    gather_load(0);
+    gather_store(0);
+    __syncthreads();
+    if (nchunk > 1) gather_load(DKC);
+    b_load(bcur, 0);
+    for (int s = 0; s < nstep; ++s) {
+        const int chunk = s >> 1, ks = s & 1;
+        if (s + 1 < nstep) b_load(bnext, (s + 1) * 32);
+        const TOP* Ab = As[chunk & 1] + ks * 32 + fq * 8;
+        fragv af[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const fragv*>(Ab + (i * 16 + fr) * LDA);
         if constexpr (sizeof(TOP) == 2) {
-            bf16x8 af[TI], bf[TJ];
 #pragma unroll
-            for (int i = 0; i < TI; ++i)
-                af[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * 16 * TI + i * 16 + fr) * LD + fq * 8]);
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < TJ; ++j)
-                bf[j] = *reinterpret_cast<const bf16x8*>(&Bs[(wn * 16 * TJ + j * 16 + fr) * LD + fq * 8]);
-#pragma unroll
-            for (int i = 0; i < TI; ++i)
-#pragma unroll
-                for (int j = 0; j < TJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < CB; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bcur[j], acc[i][j], 0, 0, 0);
         } else {
 #pragma unroll
-            for (int q = 0; q < GBK / 4; ++q) {
-                float af[TI], bf[TJ];
+            for (int e = 0; e < 8; ++e)
 #pragma unroll
-                for (int i = 0; i < TI; ++i) af[i] = As[(wm * 16 * TI + i * 16 + fr) * LD + 4 * q + fq];
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < TJ; ++j) bf[j] = Bs[(wn * 16 * TJ + j * 16 + fr) * LD + 4 * q + fq];
+                    for (int j = 0; j < CB; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][e], bcur[j][e], acc[i][j], 0, 0, 0);
+        }
 #pragma unroll
-                for (int i = 0; i < TI; ++i)
-#pragma unroll
-                    for (int j = 0; j < TJ; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
-            }
+        for (int j = 0; j < CB; ++j) bcur[j] = bnext[j];
+        if (ks == 1 && chunk + 1 < nchunk) {
+            // the buffer of chunk + 1 was last read in chunk - 1, before the previous barrier
+            gather_store((chunk + 1) & 1);
+            __syncthreads();
+            if (chunk + 2 < nchunk) gather_load((chunk + 2) * DKC);
         }
     }
 
     // x[entry] += Y[row][col] (velocity) or Y[row][col] / h (pressure);
-    // Y[row][col]: row = tile row + 4 (lane / 16) + e, col = tile col + lane % 16
+    // Y[row][col]: row = 16 i + 4 (lane / 16) + e, col = column block start + lane % 16.
+    // The 16 entries of a column block are read together and written together,
+    // and the next block's reads are issued before this block's writes (all
+    // entries of a lane are distinct, so the order is free; written entry by
+    // entry, every read would wait for the previous write).
     T* __restrict__ x = static_cast<T*>(a.x);
+    T xv[2][16];
+    auto epi_load = [&](int j, T* dst) {
+        const int col = n0 + (w * CB + j) * 16 + fr;
+        const int c = col < a.d ? comp_of(g, col) : 0, o = col < a.d ? off[col] : 0;
 #pragma unroll
-    for (int j = 0; j < TJ; ++j) {
-        const int col = n0 + wn * 16 * TJ + j * 16 + fr;
-        if (col >= a.d) continue;
-        const int c = comp_of(g, col), o = off[col];
+        for (int ie = 0; ie < 16; ++ie) {
+            const long long b = rbase[(ie >> 2) * 16 + 4 * fq + (ie & 3)][c];
+            dst[ie] = (col < a.d && b >= 0) ? x[b + o] : T(0);
+        }
+    };
+    epi_load(0, xv[0]);
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+        const int col = n0 + (w * CB + j) * 16 + fr;
+        const int c = col < a.d ? comp_of(g, col) : 0, o = col < a.d ? off[col] : 0;
         const float sc = c == 3 ? sv : 1.0f;
+        if (j + 1 < CB) epi_load(j + 1, xv[(j + 1) & 1]);
+        if (col >= a.d) continue;
 #pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int rl = wm * 16 * TI + i * 16 + 4 * fq + e;
-                if (rbase[rl][0] < 0) continue;
-                T* p = x + rbase[rl][c] + o;
-                *p = T(*p + T(acc[i][j][e] * sc));
-            }
+        for (int ie = 0; ie < 16; ++ie) {
+            const long long b = rbase[(ie >> 2) * 16 + 4 * fq + (ie & 3)][c];
+            if (b >= 0) x[b + o] = T(xv[j & 1][ie] + T(acc[ie >> 2][j][ie & 3] * sc));
+        }
     }
 }
 
-template <typename TOP, typename T, int TI>
+template <typename TOP, typename T, int CB>
 hipError_t direct_dispatch(const DirectArgs& a, hipStream_t st) {
-    constexpr int BT = 32 * TI;
-    const int tiles = ((a.rows + BT - 1) / BT) * ((a.d + BT - 1) / BT);
-    hipLaunchKernelGGL((direct_patch_kernel<TOP, T, TI, TI>), dim3(tiles), dim3(GNT), 0, st, a);
+    constexpr int BN = 4 * CB * 16;
+    const int tiles = (a.rows / DBM) * ((a.d + BN - 1) / BN);
+    hipLaunchKernelGGL((direct_patch_kernel<TOP, T, CB>), dim3(tiles), dim3(256), 0, st, a);
     return hipGetLastError();
+}
+
+template <typename TOP, typename T>
+hipError_t direct_dispatch_cb(const DirectArgs& a, hipStream_t st) {
+    return a.d <= 256 ? direct_dispatch<TOP, T, 4>(a, st) : direct_dispatch<TOP, T, 6>(a, st);
 }
 
 }  // namespace
 
 hipError_t launch_direct_patch(bool f64, bool bf16, const void* r, void* x, int n, int k, const PatchGroups& pg,
-                               const float* B, hipStream_t st) {
+                               const void* Bt, hipStream_t st) {
     const int rows = pg.ng > 0 ? pg.start[pg.ng] : 0;
     if (rows <= 0) return hipSuccess;
     DirectArgs a;
     a.r = r;
     a.x = x;
-    a.B = B;
+    a.Bt = Bt;
     a.geo = make_geo(n, k);
     a.d = a.geo.size;
-    a.bstride = size_t(a.d) * a.d;
+    int dn = 0;
+    direct_dims(a.d, &a.dk, &dn);
+    a.bstride = size_t(dn) * a.dk;
     a.rows = rows;
     a.pg = pg;
-    if (a.d > kMaxPatchDim) return hipErrorInvalidValue;
-    static_assert(kGroupAlign % 128 == 0, "a row tile must not straddle two groups");
-    // 128 x 128 tiles when they still give two workgroups per CU, else 64 x 64
-    const bool big = size_t((rows + 127) / 128) * ((a.d + 127) / 128) >= 512;
-    if (big) {
-        if (bf16) return f64 ? direct_dispatch<__bf16, double, 4>(a, st) : direct_dispatch<__bf16, float, 4>(a, st);
-        return f64 ? direct_dispatch<float, double, 4>(a, st) : direct_dispatch<float, float, 4>(a, st);
-    }
-    if (bf16) return f64 ? direct_dispatch<__bf16, double, 2>(a, st) : direct_dispatch<__bf16, float, 2>(a, st);
-    return f64 ? direct_dispatch<float, double, 2>(a, st) : direct_dispatch<float, float, 2>(a, st);
+    static_assert(kGroupAlign % DBM == 0, "a row tile must not straddle two groups");
+    if (a.dk > kMaxPatchDk || rows % DBM != 0) return hipErrorInvalidValue;
+    if (bf16) return f64 ? direct_dispatch_cb<__bf16, double>(a, st) : direct_dispatch_cb<__bf16, float>(a, st);
+    return f64 ? direct_dispatch_cb<float, double>(a, st) : direct_dispatch_cb<float, float>(a, st);
 }
 
 // ---------------------------------------------------------------- training helpers

@@ -72,11 +72,14 @@ PatchGroups colour_groups(int n, int colour, bool all_types);
 // The Direct solver on every patch of one colour (colour_groups with
 // all_types), in one launch: x[R_j] += M_type (R_j r scaled by 1/h (velocity)
 // and 1/h^2 (pressure)), the output's pressure rows scaled by 1/h, for each
-// patch j; M_type = B + mat[g] d^2, d x d row-major [in][out] FP32.  Products
-// on the matrix cores with BF16 (bf16) or FP32 operands and FP32
-// accumulation.  r and x: level vectors (double if f64, else float), distinct.
+// patch j.  Bt holds per type the map M padded with zeros to dn x dk
+// (direct_dims), row-major [out][in], BF16 (bf16) or FP32, types dn dk
+// elements apart; every pointer 16-byte aligned.  Products on the matrix
+// cores with FP32 accumulation.  r and x: level vectors (double if f64, else
+// float), distinct.
+void direct_dims(int d, int* dk, int* dn);
 hipError_t launch_direct_patch(bool f64, bool bf16, const void* r, void* x, int n, int k, const PatchGroups& pg,
-                               const float* B, hipStream_t st);
+                               const void* Bt, hipStream_t st);
 
 // Interior patches p0 .. p0+np-1 of one colour: patch-local vectors of a
 // level vector (row q of X / Y / T belongs to patch p0 + q).
