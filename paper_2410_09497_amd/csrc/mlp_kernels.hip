@@ -617,31 +617,12 @@ hipError_t launch_patch_gather_diff(bool f64, const void* xnew, const void* xold
 // ---------------------------------------------------------------- Direct solver: gather, GEMM, scatter fused
 
 void direct_dims(int d, int* dk, int* dn) {
-    const int cols = d <= 256 ? 256 : 384;   // columns of one workgroup: 4 waves x (4 or 6) blocks of 16
+    const int cols = d <= 256 ? 256 : 768;   // columns of one workgroup: 4 waves x 4 or 8 waves x 6 blocks of 16
     *dk = (d + 63) / 64 * 64;
     *dn = (d + cols - 1) / cols * cols;
 }
 
 namespace {
-
-// Patch-local entry q -> offset from its component's corner of the patch: the
-// index of entry q in the level vector is base[comp(q)] + offset(q)
-__device__ inline int local_offset(const PatchGeo& g, int q) {
-    if (q < 3 * g.nvel) {
-        const int c = q / g.nvel, w = q - c * g.nvel;
-        const int l0 = c == 0 ? g.lc : g.m, l1 = c == 1 ? g.lc : g.m;
-        const int i0 = w % l0, i1 = (w / l0) % l1, i2 = w / (l0 * l1);
-        const int e0 = c == 0 ? g.N1 - 1 : g.N1, e1 = c == 1 ? g.N1 - 1 : g.N1;
-        return i0 + e0 * (i1 + e1 * i2);
-    }
-    const int w = q - 3 * g.nvel;
-    const int i0 = w % g.m, i1 = (w / g.m) % g.m, i2 = w / (g.m * g.m);
-    return i0 + g.N1 * (i1 + g.N1 * i2);
-}
-
-__device__ inline int comp_of(const PatchGeo& g, int q) {
-    return (q >= g.nvel) + (q >= 2 * g.nvel) + (q >= 3 * g.nvel);
-}
 
 struct DirectArgs {
     const void* r;     // residual (level vector)
@@ -654,7 +635,7 @@ struct DirectArgs {
 };
 
 constexpr int kMaxPatchDk = 1856;   // k = 3: d = 3 * 7 * 64 + 512, a multiple of 64
-constexpr int DBM = 64, DKC = 64, DPAD = 8;
+constexpr int DBM = 64, DKC = 64, DPAD = 8, CLD = 17;
 
 template <typename TOP> struct Frag;
 template <> struct Frag<__bf16> {
@@ -664,26 +645,79 @@ template <> struct Frag<float> {
     typedef float v __attribute__((ext_vector_type(8)));
 };
 
-// One workgroup (4 waves) owns 64 patch rows of a colour's grouped row space
-// and 4 x CB x 16 output columns; each wave all 64 rows and CB column blocks.
-// Row i of the product is the normalized residual of patch i,
-// (r_vel / h, r_pres / h^2), gathered from the level vector; the product with
-// the patch type's map M (the row tile's group) is added into x as (U, h P)
-// -> velocity U, pressure (h P) / h.  The k range runs in chunks of 64: a
-// chunk of the gathered rows sits in LDS (double buffered: the next chunk's
-// loads are in flight during this chunk's products); the M fragments come
-// straight from global memory (L2), one k-step ahead.  A lane's fragments
-// cover 8 consecutive k of a 32-wide k-step: one 16x16x32 BF16 MFMA, or
-// eight 16x16x4 FP32 MFMAs taking the 8 k one at a time (the same k order
-// on both operands).  Within a colour the patches are disjoint, so every x
-// entry has exactly one writer.  Column tiles of a row tile run on one XCD.
-template <typename TOP, typename T, int CB>
-__global__ void __launch_bounds__(256) direct_patch_kernel(DirectArgs a) {
-    constexpr int BN = 4 * CB * 16, LDA = DKC + DPAD;
+// Tables of patch-local entry q.  off: offset from its component's corner of
+// the patch (the level-vector index is corner[comp] + off).  meta: the
+// contiguous run of q it lies on (the entries of one component that differ
+// only in the first index: consecutive in q and in memory) -- run start
+// (bits 0..11), run length (12..15), component (16..17); entries q >= d are
+// runs of their own.
+__device__ inline void entry_tables(const PatchGeo& g, int d, int q, int& off, int& meta) {
+    if (q >= d) {
+        off = 0;
+        meta = q | (1 << 12);
+        return;
+    }
+    int c, w, l0, l1, e0, e1;
+    if (q < 3 * g.nvel) {
+        c = q / g.nvel;
+        w = q - c * g.nvel;
+        l0 = c == 0 ? g.lc : g.m;
+        l1 = c == 1 ? g.lc : g.m;
+        e0 = c == 0 ? g.N1 - 1 : g.N1;
+        e1 = c == 1 ? g.N1 - 1 : g.N1;
+    } else {
+        c = 3;
+        w = q - 3 * g.nvel;
+        l0 = l1 = g.m;
+        e0 = e1 = g.N1;
+    }
+    const int i0 = w % l0, i1 = (w / l0) % l1, i2 = w / (l0 * l1);
+    off = i0 + e0 * (i1 + e1 * i2);
+    meta = (q - i0) | (l0 << 12) | (c << 16);
+}
+
+// Element e (e < 64 W) of the 64 rows x [qw, qw + W) window, taken run
+// segment by run segment (a run clipped to the window), and in a segment row
+// by row with q fastest: consecutive e are consecutive entries of one patch
+// and then the same entries of the next patch, which for neighbouring
+// patches of a colour lie next to each other in memory.
+__device__ inline void window_entry(const int* __restrict__ meta, int e, int qw, int W, int& row, int& q, int& c) {
+    const int mt = meta[qw + (e >> 6)];
+    const int ls = mt & 0xfff, l0 = (mt >> 12) & 15;
+    const int ss = max(ls, qw), len = min(ls + l0, qw + W) - ss;
+    const int rel = e - ((ss - qw) << 6);
+    // rel < 64 len <= 512: (rel + 1/2) / len is at least 1/16 from an integer, far above the rounding
+    row = int((float(rel) + 0.5f) * (1.0f / float(len)));
+    q = ss + rel - row * len;
+    c = mt >> 16;
+}
+
+// One workgroup (NW waves) owns 64 patch rows of a colour's grouped row
+// space and NW x CB x 16 output columns (every column at k = 1, 2); each wave
+// all 64 rows and CB column blocks.  Row i of the product is the normalized
+// residual of patch i, (r_vel / h, r_pres / h^2), gathered from the level
+// vector; the product with the patch type's map M (the row tile's group) is
+// added into x as (U, h P) -> velocity U, pressure (h P) / h.
+//   k loop: chunks of 64; a chunk of the gathered rows sits in LDS (double
+//   buffered: the next chunk's loads are in flight during this chunk's
+//   products), gathered along contiguous runs (window_entry); the M
+//   fragments come straight from global memory (L2), one k-step ahead.  A
+//   lane's fragments cover 8 consecutive k of a 32-wide k-step: one 16x16x32
+//   BF16 MFMA, or eight 16x16x4 FP32 MFMAs taking the 8 k one at a time (the
+//   same k order on both operands).
+//   Epilogue: column block by column block through LDS, then along
+//   contiguous runs into x (read all, then write all).  Within a colour the
+//   patches are disjoint, so every x entry has exactly one writer.
+// Column tiles of a row tile run on one XCD.
+template <typename TOP, typename T, int NW, int CB>
+__global__ void __launch_bounds__(64 * NW) direct_patch_kernel(DirectArgs a) {
+    constexpr int NT = 64 * NW, BN = NW * CB * 16, LDA = DKC + DPAD, EPT = DBM * DKC / NT;
     typedef typename Frag<TOP>::v fragv;
     __shared__ __attribute__((aligned(32))) TOP As[2][DBM * LDA];
     __shared__ int off[kMaxPatchDk];
+    __shared__ int meta[kMaxPatchDk];
     __shared__ long long rbase[DBM][4];
+    __shared__ float Cs[NW][DBM * CLD];
 
     const PatchGeo& g = a.geo;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -692,7 +726,7 @@ __global__ void __launch_bounds__(256) direct_patch_kernel(DirectArgs a) {
     const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
     const int m0 = (tile / ntn) * DBM, n0 = (tile % ntn) * BN;
 
-    for (int q = t; q < a.dk; q += 256) off[q] = q < a.d ? local_offset(g, q) : 0;
+    for (int q = t; q < a.dk; q += NT) entry_tables(g, a.d, q, off[q], meta[q]);
     if (t < DBM) {
         int v[3];
         if (m0 + t < a.rows && group_vertex(a.pg, m0 + t, v)) {
@@ -714,31 +748,23 @@ __global__ void __launch_bounds__(256) direct_patch_kernel(DirectArgs a) {
     }
     __syncthreads();
 
-    // gather: thread t loads row gr = t mod 64 at k = k0 + w + 4 i (i < 16), wave-uniform k
-    const int gr = t & 63;
-    long long rb[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) rb[c] = rbase[gr][c];
-    const bool rvalid = rb[0] >= 0;
     const T* __restrict__ r = static_cast<const T*>(a.r);
     const float sv = float(g.n), sp = float(g.n) * float(g.n);   // 1/h and 1/h^2, powers of two
-    float gv[DKC / 4];
+    float gv[EPT];
+    int gpos[EPT];   // row * LDA + q - k0 of each staged value
     auto gather_load = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < DKC / 4; ++i) {
-            const int q = k0 + w + 4 * i;
-            float val = 0.0f;
-            if (rvalid && q < a.d) {
-                const int c = comp_of(g, q);
-                val = float(r[rb[c] + off[q]]) * (c == 3 ? sp : sv);
-            }
-            gv[i] = val;
+        for (int i = 0; i < EPT; ++i) {
+            int row, q, c;
+            window_entry(meta, t + NT * i, k0, DKC, row, q, c);
+            gpos[i] = row * LDA + q - k0;
+            const long long b = rbase[row][c];
+            gv[i] = (q < a.d && b >= 0) ? float(r[b + off[q]]) * (c == 3 ? sp : sv) : 0.0f;
         }
     };
     auto gather_store = [&](int buf) {
-        TOP* dst = As[buf] + gr * LDA + w;
 #pragma unroll
-        for (int i = 0; i < DKC / 4; ++i) dst[4 * i] = TOP(gv[i]);
+        for (int i = 0; i < EPT; ++i) As[buf][gpos[i]] = TOP(gv[i]);
     };
 
     // M fragments: lane (fr, fq) of column block j reads M[col][k .. k + 7], col = n0 + (w CB + j) 16 + fr
@@ -795,50 +821,58 @@ __global__ void __launch_bounds__(256) direct_patch_kernel(DirectArgs a) {
         }
     }
 
-    // x[entry] += Y[row][col] (velocity) or Y[row][col] / h (pressure);
-    // Y[row][col]: row = 16 i + 4 (lane / 16) + e, col = column block start + lane % 16.
-    // The 16 entries of a column block are read together and written together,
-    // and the next block's reads are issued before this block's writes (all
-    // entries of a lane are distinct, so the order is free; written entry by
-    // entry, every read would wait for the previous write).
+    // epilogue: block (rows 16 i + 4 (lane / 16) + e, columns lane % 16) -> Cs[w], then along runs into x
     T* __restrict__ x = static_cast<T*>(a.x);
-    T xv[2][16];
-    auto epi_load = [&](int j, T* dst) {
-        const int col = n0 + (w * CB + j) * 16 + fr;
-        const int c = col < a.d ? comp_of(g, col) : 0, o = col < a.d ? off[col] : 0;
-#pragma unroll
-        for (int ie = 0; ie < 16; ++ie) {
-            const long long b = rbase[(ie >> 2) * 16 + 4 * fq + (ie & 3)][c];
-            dst[ie] = (col < a.d && b >= 0) ? x[b + o] : T(0);
-        }
-    };
-    epi_load(0, xv[0]);
+    float* cw = Cs[w];
 #pragma unroll
     for (int j = 0; j < CB; ++j) {
-        const int col = n0 + (w * CB + j) * 16 + fr;
-        const int c = col < a.d ? comp_of(g, col) : 0, o = col < a.d ? off[col] : 0;
-        const float sc = c == 3 ? sv : 1.0f;
-        if (j + 1 < CB) epi_load(j + 1, xv[(j + 1) & 1]);
-        if (col >= a.d) continue;
+        const int qw = n0 + (w * CB + j) * 16, W = min(16, a.d - qw);
+        __syncthreads();   // previous block's Cs fully read
 #pragma unroll
-        for (int ie = 0; ie < 16; ++ie) {
-            const long long b = rbase[(ie >> 2) * 16 + 4 * fq + (ie & 3)][c];
-            if (b >= 0) x[b + o] = T(xv[j & 1][ie] + T(acc[ie >> 2][j][ie & 3] * sc));
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cw[(i * 16 + 4 * fq + e) * CLD + fr] = acc[i][j][e];
+        __syncthreads();
+        if (W <= 0) continue;
+        long long idx[16];
+        T xv[16];
+        float yv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = lane + 64 * i;
+            idx[i] = -1;
+            if (e < 64 * W) {
+                int row, q, c;
+                window_entry(meta, e, qw, W, row, q, c);
+                const long long b = rbase[row][c];
+                if (b >= 0) {
+                    idx[i] = b + off[q];
+                    yv[i] = cw[row * CLD + q - qw] * (c == 3 ? sv : 1.0f);
+                }
+            }
+            xv[i] = idx[i] >= 0 ? x[idx[i]] : T(0);
         }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (idx[i] >= 0) x[idx[i]] = T(xv[i] + T(yv[i]));
     }
 }
 
-template <typename TOP, typename T, int CB>
+template <typename TOP, typename T, int NW, int CB>
 hipError_t direct_dispatch(const DirectArgs& a, hipStream_t st) {
-    constexpr int BN = 4 * CB * 16;
+    constexpr int BN = NW * CB * 16;
     const int tiles = (a.rows / DBM) * ((a.d + BN - 1) / BN);
-    hipLaunchKernelGGL((direct_patch_kernel<TOP, T, CB>), dim3(tiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((direct_patch_kernel<TOP, T, NW, CB>), dim3(tiles), dim3(64 * NW), 0, st, a);
     return hipGetLastError();
 }
 
+// 8 waves x 6 column blocks = 768 columns (every column at k = 2); FP32 operands
+// take twice the fragment registers: 8 x 3 (384 columns, a divisor of 768)
 template <typename TOP, typename T>
 hipError_t direct_dispatch_cb(const DirectArgs& a, hipStream_t st) {
-    return a.d <= 256 ? direct_dispatch<TOP, T, 4>(a, st) : direct_dispatch<TOP, T, 6>(a, st);
+    if (a.d <= 256) return direct_dispatch<TOP, T, 4, 4>(a, st);
+    if constexpr (sizeof(TOP) == 2) return direct_dispatch<TOP, T, 8, 6>(a, st);
+    else return direct_dispatch<TOP, T, 8, 3>(a, st);
 }
 
 }  // namespace
