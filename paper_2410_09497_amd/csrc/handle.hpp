@@ -24,7 +24,8 @@ struct stokesmg {
     std::vector<size_t> tab_f64, tab_f32;    // per level
     std::vector<size_t> ptab_f64, ptab_f32;  // per level (patch tables; unused for n < 2)
     size_t r_vec = 0;                        // residual vector of the finest level (8 B per unknown)
-    size_t c_vec = 0;                        // correction vector of the finest level (pair capture)
+    size_t c_vec = 0;                        // finest-level vector: pair capture's correction (inside a
+                                             // sweep), the transfers' intermediates (between sweeps)
     size_t cg_counter = 0;                   // two 64-bit counters: CG iterations, patch solves
     size_t ws_needed = 0;
 

@@ -9,79 +9,66 @@ namespace {
 
 constexpr int NT = 256;
 
-// level geometry for the layout [u_x | u_y | u_z | p]
-struct Geo {
-    int N1;
-    size_t nc;
-    __device__ void decode(size_t i, int& comp, int& X, int& Y, int& Z) const {
-        const size_t np = size_t(N1) * N1 * N1;
-        (void)np;
-        if (i < 3 * nc) {
-            comp = int(i / nc);
-            size_t e = i - size_t(comp) * nc;
-            const int ex = comp == 0 ? N1 - 1 : N1, ey = comp == 1 ? N1 - 1 : N1;
-            X = int(e % ex);
-            e /= ex;
-            Y = int(e % ey);
-            Z = int(e / ey);
-        } else {
-            comp = 3;
-            size_t e = i - 3 * nc;
-            X = int(e % N1);
-            e /= N1;
-            Y = int(e % N1);
-            Z = int(e / N1);
-        }
-    }
-    __device__ size_t encode(int comp, int X, int Y, int Z) const {
-        if (comp == 3) return 3 * nc + X + size_t(N1) * (Y + size_t(N1) * Z);
-        const int ex = comp == 0 ? N1 - 1 : N1, ey = comp == 1 ? N1 - 1 : N1;
-        return size_t(comp) * nc + X + size_t(ex) * (Y + size_t(ey) * Z);
-    }
+// One 1D pass of a tensor-product transfer: for every component c, along
+// `axis`, out_c(..., P, ...) (+)= sum_a w[P][a] in_c(..., idx[P][a], ...), with
+// the continuous-direction lists when axis == c and the DG lists otherwise.
+// Arrays [Z][Y][X] per component, X fastest, components one after another.
+struct Pass {
+    int ein[4][3], eout[4][3];
+    size_t oin[4], oout[4];
+    int axis;
+    const int* li[2];       // [0]: DG lists, [1]: continuous lists (idx; -1 = unused)
+    const double* lw[2];
+    int w[2];
 };
 
-// out[i] (+)= sum over the tensor product of three 1D row lists of in[...]
-// dg / cn: row lists of the DG and continuous directions (idx, weight), widths wd / wc
+constexpr int PX = 128, PY = 2;
+
+// block (PX, PY): rows Y = blockIdx.x PY + threadIdx.y, plane Z = blockIdx.y, component blockIdx.z
 template <typename T, bool ACC>
-__global__ void __launch_bounds__(NT)
-tensor_transfer(const T* __restrict__ in, T* __restrict__ out, Geo go, Geo gi, const int* __restrict__ dgi,
-                const double* __restrict__ dgw, int wd, const int* __restrict__ cni, const double* __restrict__ cnw,
-                int wc, size_t total) {
-    const size_t i = size_t(blockIdx.x) * NT + threadIdx.x;
-    if (i >= total) return;
-    int comp, X, Y, Z;
-    go.decode(i, comp, X, Y, Z);
-    const int P[3] = {X, Y, Z};
-    const int* li[3];
-    const double* lw[3];
-    int wdt[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const bool cont = d == comp;
-        li[d] = cont ? cni + size_t(P[d]) * wc : dgi + size_t(P[d]) * wd;
-        lw[d] = cont ? cnw + size_t(P[d]) * wc : dgw + size_t(P[d]) * wd;
-        wdt[d] = cont ? wc : wd;
-    }
-    double acc = 0.0;
-    for (int c = 0; c < wdt[2]; ++c) {
-        const int iz = li[2][c];
-        if (iz < 0) continue;
-        const double wz = lw[2][c];
-        for (int b = 0; b < wdt[1]; ++b) {
-            const int iy = li[1][b];
-            if (iy < 0) continue;
-            const double wzy = wz * lw[1][b];
-            for (int a = 0; a < wdt[0]; ++a) {
-                const int ix = li[0][a];
-                if (ix < 0) continue;
-                acc += wzy * lw[0][a] * double(in[gi.encode(comp, ix, iy, iz)]);
-            }
+__global__ void __launch_bounds__(PX * PY) transfer_pass(const T* __restrict__ in, T* __restrict__ out, Pass p) {
+    const int c = blockIdx.z;
+    const int ex = p.eout[c][0], ey = p.eout[c][1], ez = p.eout[c][2];
+    const int Y = blockIdx.x * PY + threadIdx.y, Z = blockIdx.y;
+    if (Y >= ey || Z >= ez) return;
+    const int kind = p.axis == c ? 1 : 0;
+    const int* __restrict__ li = p.li[kind];
+    const double* __restrict__ lw = p.lw[kind];
+    const int w = p.w[kind];
+    const int ix = p.ein[c][0], iy = p.ein[c][1];
+    const T* src = in + p.oin[c];
+    T* dst = out + p.oout[c] + size_t(ex) * (Y + size_t(ey) * Z);
+    for (int X = threadIdx.x; X < ex; X += PX) {
+        const int P = p.axis == 0 ? X : (p.axis == 1 ? Y : Z);
+        double acc = 0.0;
+        for (int a = 0; a < w; ++a) {
+            const int j = li[P * w + a];
+            if (j < 0) continue;
+            const int xi = p.axis == 0 ? j : X, yi = p.axis == 1 ? j : Y, zi = p.axis == 2 ? j : Z;
+            acc += lw[P * w + a] * double(src[xi + size_t(ix) * (yi + size_t(iy) * zi)]);
         }
+        if (ACC)
+            dst[X] += T(acc);
+        else
+            dst[X] = T(acc);
     }
-    if (ACC)
-        out[i] += T(acc);
+}
+
+template <typename T>
+hipError_t run_pass(const void* in, void* out, const Pass& p, bool acc, hipStream_t st) {
+    int my = 0, mz = 0;
+    for (int c = 0; c < 4; ++c) {
+        my = my > p.eout[c][1] ? my : p.eout[c][1];
+        mz = mz > p.eout[c][2] ? mz : p.eout[c][2];
+    }
+    const dim3 grid((my + PY - 1) / PY, mz, 4), block(PX, PY);
+    if (acc)
+        hipLaunchKernelGGL((transfer_pass<T, true>), grid, block, 0, st, static_cast<const T*>(in), static_cast<T*>(out),
+                           p);
     else
-        out[i] = T(acc);
+        hipLaunchKernelGGL((transfer_pass<T, false>), grid, block, 0, st, static_cast<const T*>(in),
+                           static_cast<T*>(out), p);
+    return hipGetLastError();
 }
 
 // x = K0^+ b with the FP64 matrix (row-major n x n); vectors in T
@@ -194,27 +181,50 @@ unsigned blocks_for(size_t n) { return unsigned((n + NT - 1) / NT); }
 }  // namespace
 
 hipError_t launch_transfer(bool f64, bool acc, const void* in, void* out, int N1_out, int N1_in, const int* dgi,
-                           const double* dgw, int wd, const int* cni, const double* cnw, int wc, hipStream_t st) {
-    Geo go{N1_out, size_t(N1_out - 1) * N1_out * N1_out};
-    Geo gi{N1_in, size_t(N1_in - 1) * N1_in * N1_in};
-    const size_t total = 3 * go.nc + size_t(N1_out) * N1_out * N1_out;
-    const unsigned g = blocks_for(total);
-    if (f64) {
-        if (acc)
-            hipLaunchKernelGGL((tensor_transfer<double, true>), dim3(g), dim3(NT), 0, st, static_cast<const double*>(in),
-                               static_cast<double*>(out), go, gi, dgi, dgw, wd, cni, cnw, wc, total);
-        else
-            hipLaunchKernelGGL((tensor_transfer<double, false>), dim3(g), dim3(NT), 0, st, static_cast<const double*>(in),
-                               static_cast<double*>(out), go, gi, dgi, dgw, wd, cni, cnw, wc, total);
-    } else {
-        if (acc)
-            hipLaunchKernelGGL((tensor_transfer<float, true>), dim3(g), dim3(NT), 0, st, static_cast<const float*>(in),
-                               static_cast<float*>(out), go, gi, dgi, dgw, wd, cni, cnw, wc, total);
-        else
-            hipLaunchKernelGGL((tensor_transfer<float, false>), dim3(g), dim3(NT), 0, st, static_cast<const float*>(in),
-                               static_cast<float*>(out), go, gi, dgi, dgw, wd, cni, cnw, wc, total);
+                           const double* dgw, int wd, const int* cni, const double* cnw, int wc, void* tmp,
+                           hipStream_t st) {
+    // extents per component along x, y, z: N1 - 1 in the component's own (continuous) direction, else N1
+    auto ext = [](int N1, int c, int d) { return c == d ? N1 - 1 : N1; };
+    int cur[4][3];
+    for (int c = 0; c < 4; ++c)
+        for (int d = 0; d < 3; ++d) cur[c][d] = ext(N1_in, c, d);
+    const size_t esz = f64 ? sizeof(double) : sizeof(float);
+    char* bufs[2] = {static_cast<char*>(tmp), nullptr};
+    const void* src = in;
+    for (int axis = 0; axis < 3; ++axis) {
+        Pass p{};
+        p.axis = axis;
+        p.li[0] = dgi;
+        p.lw[0] = dgw;
+        p.w[0] = wd;
+        p.li[1] = cni;
+        p.lw[1] = cnw;
+        p.w[1] = wc;
+        size_t oi = 0, oo = 0;
+        for (int c = 0; c < 4; ++c) {
+            for (int d = 0; d < 3; ++d) {
+                p.ein[c][d] = cur[c][d];
+                p.eout[c][d] = d == axis ? ext(N1_out, c, d) : cur[c][d];
+            }
+            p.oin[c] = oi;
+            p.oout[c] = oo;
+            oi += size_t(p.ein[c][0]) * p.ein[c][1] * p.ein[c][2];
+            oo += size_t(p.eout[c][0]) * p.eout[c][1] * p.eout[c][2];
+        }
+        // passes 0 and 1 write the temporaries (the second right after the first), pass 2 the output
+        void* dst = out;
+        if (axis < 2) {
+            if (axis == 1) bufs[1] = bufs[0] + (oi * esz + 255) / 256 * 256;
+            dst = bufs[axis];
+        }
+        const hipError_t e = f64 ? run_pass<double>(src, dst, p, axis == 2 && acc, st)
+                                 : run_pass<float>(src, dst, p, axis == 2 && acc, st);
+        if (e != hipSuccess) return e;
+        for (int c = 0; c < 4; ++c)
+            for (int d = 0; d < 3; ++d) cur[c][d] = p.eout[c][d];
+        src = dst;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t launch_coarse_gemv(bool f64, const double* A, const void* b, void* x, int n, hipStream_t st) {

@@ -11,8 +11,12 @@ namespace smg {
 // out (+)= T_3D in, with T_3D the tensor product of 1D row lists: the
 // continuous list in a component's own direction, the DG list otherwise
 // (prolongation: out fine, in coarse; restriction: the transposed lists).
+// Applied as three 1D passes (x, y, z) through two intermediates in `tmp`,
+// which needs room for 3/4 of the larger level's vector plus 256 bytes
+// (device; distinct from in and out).
 hipError_t launch_transfer(bool f64, bool acc, const void* in, void* out, int N1_out, int N1_in, const int* dgi,
-                           const double* dgw, int wd, const int* cni, const double* cnw, int wc, hipStream_t st);
+                           const double* dgw, int wd, const int* cni, const double* cnw, int wc, void* tmp,
+                           hipStream_t st);
 
 // x = A b, A dense FP64 (n x n row-major), b and x in FP64 or FP32
 hipError_t launch_coarse_gemv(bool f64, const double* A, const void* b, void* x, int n, hipStream_t st);

@@ -44,12 +44,12 @@ int vcycle_level(stokesmg* h, int l, bool f64, const void* b, void* x, hipStream
     SMG_HIP(h, smg::launch_transfer(f64, false, r, bc, N1c, N1f, reinterpret_cast<const int*>(w + o.rd_i),
                                     reinterpret_cast<const double*>(w + o.rd_w), o.wrd,
                                     reinterpret_cast<const int*>(w + o.rc_i),
-                                    reinterpret_cast<const double*>(w + o.rc_w), o.wrc, st));
+                                    reinterpret_cast<const double*>(w + o.rc_w), o.wrc, w + h->c_vec, st));
     if (int rc = vcycle_level(h, l - 1, f64, bc, xc, st, cap)) return rc;
     SMG_HIP(h, smg::launch_transfer(f64, true, xc, x, N1f, N1c, reinterpret_cast<const int*>(w + o.pd_i),
                                     reinterpret_cast<const double*>(w + o.pd_w), o.wpd,
                                     reinterpret_cast<const int*>(w + o.pc_i),
-                                    reinterpret_cast<const double*>(w + o.pc_w), o.wpc, st));
+                                    reinterpret_cast<const double*>(w + o.pc_w), o.wpc, w + h->c_vec, st));
     // post-smoothing
     return smg::smooth_sweep(h, l, f64, x, b, st, lc);
 }
