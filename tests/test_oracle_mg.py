@@ -145,3 +145,68 @@ def test_mg_fgmres_iterations_level_robust(n, k, max_it):
     assert len(hist) - 1 <= max_it
     r = b - K @ x
     assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b)
+
+
+def _dense_gmres_history(T, b, steps):
+    """Relative residuals min ||b - T y|| / ||b|| over the Krylov spaces
+    K_m(T, b), m = 0..steps: Arnoldi with modified Gram-Schmidt twice, then
+    the small least-squares problem solved directly at every m."""
+    nb = np.linalg.norm(b)
+    Q = np.zeros((len(b), steps + 1))
+    H = np.zeros((steps + 1, steps))
+    Q[:, 0] = b / nb
+    hist = [1.0]
+    for m in range(steps):
+        w = T @ Q[:, m]
+        for _ in range(2):
+            for i in range(m + 1):
+                c = Q[:, i] @ w
+                H[i, m] += c
+                w = w - c * Q[:, i]
+        H[m + 1, m] = np.linalg.norm(w)
+        Q[:, m + 1] = w / H[m + 1, m]
+        e1 = np.zeros(m + 2)
+        e1[0] = nb
+        y = np.linalg.lstsq(H[:m + 2, :m + 1], e1, rcond=None)[0]
+        hist.append(np.linalg.norm(e1 - H[:m + 2, :m + 1] @ y) / nb)
+    return hist
+
+
+def test_vcycle_spectrum_and_fgmres_steps():
+    """The V-cycle as a dense operator at 4^3 cells, k = 1 (Sec. 3; the
+    columns of P^-1 are V-cycles of the unit vectors, computed in blocks).
+    Pins:
+    - T = K P^-1 has exactly one zero eigenvalue (the constant pressure,
+      the kernel of K) and every other eigenvalue mu has |1 - mu| <= 0.4
+      (measured 0.357): the V-cycle is a contraction on the complement;
+    - FGMRES with the V-cycle (a fixed linear preconditioner) takes the
+      iterates of right-preconditioned GMRES, so its residual history on
+      the sine problem equals that of GMRES on the dense T, computed here
+      by an independent Arnoldi process with least squares at every step;
+      the step count to 1e-8 it predicts is the oracle's."""
+    mg = Multigrid(4, 1)
+    S, K = mg.fine["S"], mg.fine["K"]
+    N = S.ndof
+    Pinv = np.zeros((N, N))
+    for j0 in range(0, N, 128):
+        m = min(128, N - j0)
+        E = np.zeros((N, m))
+        E[np.arange(j0, j0 + m), np.arange(m)] = 1.0
+        Pinv[:, j0:j0 + m] = mg.vcycle(E)
+    # the block V-cycle is the column-wise one
+    e = np.zeros(N)
+    e[N // 3] = 1.0
+    assert np.abs(Pinv[:, N // 3] - mg.vcycle(e)).max() <= 1e-12 * np.abs(Pinv).max()
+    T = K @ Pinv
+    mu = np.linalg.eigvals(T)
+    mu = mu[np.argsort(np.abs(mu))]
+    assert abs(mu[0]) <= 1e-10 and abs(mu[1]) >= 0.1
+    rho = np.abs(1.0 - mu[1:]).max()
+    assert rho <= 0.4, rho
+    b = S.rhs(mf.sine_f, mf.sine_u)
+    _, hist = fgmres(lambda v: K @ v, b, lambda v: mg.vcycle(v), rtol=1e-8, restart=30)
+    dense = _dense_gmres_history(T, b, len(hist) - 1)
+    for j, (a, d) in enumerate(zip(hist, dense)):
+        assert abs(a - d) <= 1e-6 * d, (j, a, d)
+    predicted = next(m for m, r in enumerate(dense) if r <= 1e-8)
+    assert predicted == len(hist) - 1

@@ -106,7 +106,7 @@ def test_mismatch_is_detected():
     assert np.abs(S2.assemble() @ xi - b).max() > 1e-3
 
 
-@pytest.mark.parametrize("k,ns", [(1, (4, 8)), (2, (2, 4)), (3, (2, 4))])
+@pytest.mark.parametrize("k,ns", [(1, (4, 8)), (2, (2, 4)), (2, (4, 8)), (3, (2, 4))])
 def test_convergence_order(k, ns):
     errs = []
     for n in ns:
