@@ -158,8 +158,9 @@ int stokesmg_cg_stats(stokesmg_t* h, int64_t* iterations, int64_t* solves, int r
  * restriction P^T, recursion, prolongation P (the canonical embedding of the
  * coarse space), post-smoothing (one sweep); on the coarsest level the dense
  * pseudo-inverse of K_0 (FP64 matrix also inside an FP32 cycle).  dtype F64
- * or F32 for b and x (finest-level vectors).  Requires degree <= 3 and a
- * coarsest level with at most 1000 unknowns (EUNSUPPORTED otherwise). */
+ * or F32 for b and x (finest-level vectors).  Requires a coarsest level with
+ * at most 1000 unknowns (EUNSUPPORTED otherwise); every degree 1..5.  The
+ * local solver is the one set by stokesmg_set_local_solver (exact by default). */
 int vcycle(stokesmg_t* h, int dtype, const void* b, void* x, void* stream);
 
 #define STOKESMG_MAX_HISTORY 512
