@@ -181,7 +181,8 @@ def _run(mg, b, log, name, solver="exact", mode="bf16", vcycle="f32", rho_ref=0.
     out = {"seconds": info["seconds"], "iterations": info["iterations"], "rel_residual": info["rel_residual"],
            "converged": info["converged"], "nu": info["nu"], "history": info["history"],
            "avg_local_cg": info["cg_iterations"] / max(info["local_solves"], 1),
-           "local_solver": solver, "vcycle": vcycle, "operands": mode if solver != "exact" else None}
+           "local_solver": solver, "vcycle": vcycle,
+           "operands": "bf16" if solver == "exact_bf16" else (mode if solver != "exact" else None)}
     if solver == "mlp":
         fb = info["fallback_iteration"]
         out.update(fallback_iteration=fb, rho_ref=rho_ref, fallback_bound=max(2 * rho_ref, 1e-3),
@@ -236,8 +237,10 @@ def train_network(dev, k, pairs, epochs, log):
 def solve_section(dev, k, n_solve, log):
     """Time to 1e-8 (wall time of solve()) of FGMRES(8) with the V-cycle on
     n_solve^3 cells.  The manufactured sine problem: all-FP64 multigrid, the
-    FP32 V-cycle, and the FP32 V-cycle whose interior local solves are the
-    Direct solver on the matrix cores (BF16 and FP32 operands).  Random smooth
+    FP32 V-cycle, the FP32 V-cycle whose local solves are the Direct solver on
+    the matrix cores (BF16 and FP32 operands), and the FP32 V-cycle whose
+    Schur CG takes its in-plane eigenbasis products on the matrix cores (BF16
+    operands).  Random smooth
     right-hand sides from an unseen seed: the same, plus the learned local
     solver (the network in place of the interior local solves, with the
     exact-solver fallback) and the network's pressure as the start of the
@@ -259,7 +262,8 @@ def solve_section(dev, k, n_solve, log):
     sine["fp32_mg"] = _run(mg, b, log, "sine fp32_mg")
     sine["fp32_direct_bf16"] = _run(mg, b, log, "sine fp32_direct_bf16", "direct", "bf16")
     sine["fp32_direct_f32"] = _run(mg, b, log, "sine fp32_direct_f32", "direct", "f32")
-    for v in ("fp32_mg", "fp32_direct_bf16", "fp32_direct_f32"):
+    sine["fp32_fd_bf16"] = _run(mg, b, log, "sine fp32_fd_bf16", "exact_bf16")
+    for v in ("fp32_mg", "fp32_direct_bf16", "fp32_direct_f32", "fp32_fd_bf16"):
         sine[v + "_speedup_vs_fp64"] = sine["fp64_mg"]["seconds"] / sine[v]["seconds"]
     out["sine"] = sine
     h = sine["fp32_mg"]["history"]

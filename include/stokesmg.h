@@ -266,6 +266,14 @@ int stokesmg_rhs_fourier(stokesmg_t* h, int level, int n_modes, const int* kappa
                                     operands per mlp_mode, FP32 accumulation) and adds the
                                     corrections; no local iteration.  Needs stokesmg_direct_setup(). */
 
+#define STOKESMG_LOCAL_EXACT_BF16 4 /* the exact Schur CG of Sec. 3.2 on every patch, with the in-plane
+                                    eigenbasis products of the fast diagonalization (S_x (x) S_y per
+                                    velocity component, all z-slices as one GEMM) on the matrix cores:
+                                    BF16 operands, FP32 accumulation (Sec. 4.3's mixed precision
+                                    carried into the local solver); the z factor and the eigenvalue
+                                    scaling in FP32.  FP32 cycles only (an FP64 sweep returns
+                                    EINVAL), degrees 1..3 (EUNSUPPORTED).  mlp_mode is ignored. */
+
 /* d (network width in and out) and P (parameter count) for the handle's degree. */
 int mlp_dims(const stokesmg_t* h, int64_t* d, int64_t* n_params);
 

@@ -305,8 +305,10 @@ class StokesMG:
         return [hist[i] for i in range(epochs)]
 
     def set_local_solver(self, solver="exact", mode="bf16", damping=1.0):
-        self._check(_lib.lib.stokesmg_set_local_solver(self._h, {"exact": 0, "mlp": 1, "mlp_warm": 2, "direct": 3}[solver], self._mode(mode),
-                                                       float(damping)))
+        """exact (Schur CG), mlp, mlp_warm, direct, or exact_bf16 (Schur CG with
+        the in-plane eigenbasis products on the matrix cores; FP32 cycles)."""
+        codes = {"exact": 0, "mlp": 1, "mlp_warm": 2, "direct": 3, "exact_bf16": 4}
+        self._check(_lib.lib.stokesmg_set_local_solver(self._h, codes[solver], self._mode(mode), float(damping)))
 
     def l2_error(self, x, level=-1):
         """(||u - u_h||, ||p - p_h||) of the FP64 level vector x against the

@@ -227,8 +227,11 @@ int smooth_sweep(stokesmg* h, int level, bool f64, void* x, const void* b, hipSt
     const bool learned = h->local_solver == STOKESMG_LOCAL_MLP && !cap;
     const bool warm = h->local_solver == STOKESMG_LOCAL_MLP_WARM && !cap;
     const bool direct = h->local_solver == STOKESMG_LOCAL_DIRECT && !cap;
+    const bool exact_mf = h->local_solver == STOKESMG_LOCAL_EXACT_BF16 && !cap;
     if (direct && !h->mlp.direct_ready)
         return h->fail(STOKESMG_EINVAL, "the Direct solver needs stokesmg_direct_setup() after mlp_set_workspace()");
+    if (exact_mf && f64)
+        return h->fail(STOKESMG_EINVAL, "the BF16 eigenbasis products run in an FP32 cycle (dtype F32)");
     const size_t N = size_t(level_total(h, level));
     for (int c = 0; c < 8; ++c) {
         SMG_HIP(h, launch_apply(k, f64, true, x, b, r, tab, n, st));
@@ -257,6 +260,8 @@ int smooth_sweep(stokesmg* h, int level, bool f64, void* x, const void* b, hipSt
             if (int rc = mlp_interior_solve(h, level, f64, x, r, c, st)) return rc;
         } else if (direct) {
             if (int rc = direct_solve(h, level, f64, x, r, c, st)) return rc;
+        } else if (exact_mf) {
+            SMG_HIP(h, launch_patch_solve_mf(k, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters, st));
         } else if (warm && interior_count(n, c) > 0) {
             SMG_HIP(h, launch_patch_solve(k, f64, x, r, ptab, n, c, h->cfg.cg_rtol, h->cfg.cg_max_it, counters,
                                           true, st));
@@ -448,13 +453,16 @@ int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode, dou
     if (!h) return STOKESMG_EINVAL;
     if (!(mlp_damping > 0.0 && mlp_damping <= 1.0)) return h->fail(STOKESMG_EINVAL, "mlp_damping must be in (0, 1]");
     if (local_solver != STOKESMG_LOCAL_EXACT && local_solver != STOKESMG_LOCAL_MLP &&
-        local_solver != STOKESMG_LOCAL_MLP_WARM && local_solver != STOKESMG_LOCAL_DIRECT)
+        local_solver != STOKESMG_LOCAL_MLP_WARM && local_solver != STOKESMG_LOCAL_DIRECT &&
+        local_solver != STOKESMG_LOCAL_EXACT_BF16)
         return h->fail(STOKESMG_EINVAL, "unknown local solver");
+    if (local_solver == STOKESMG_LOCAL_EXACT_BF16 && h->cfg.k > 3)
+        return h->fail(STOKESMG_EUNSUPPORTED, "the BF16 eigenbasis products are built for degrees 1..3");
     if (int rc = check_mode(h, mlp_mode)) return rc;
     if (local_solver == STOKESMG_LOCAL_DIRECT) {
         if (!h->mlp.ws || !h->mlp.direct_ready)
             return h->fail(STOKESMG_EINVAL, "the Direct solver needs stokesmg_direct_setup() first");
-    } else if (local_solver != STOKESMG_LOCAL_EXACT) {
+    } else if (local_solver == STOKESMG_LOCAL_MLP || local_solver == STOKESMG_LOCAL_MLP_WARM) {
         if (int rc = check_mlp(h, true)) return rc;
     }
     h->local_solver = local_solver;

@@ -19,14 +19,14 @@ int count_interior(int n, int parity) {
     return (n - 2 >= first) ? (n - 2 - first) / 2 + 1 : 0;
 }
 
-template <int K, typename T, int NTP>
+template <int K, typename T, int NTP, bool MF = false>
 hipError_t launch_nt(void* x, const void* r, const void* ptab, int n, int colour, double rtol, int maxit,
                      unsigned long long* counters, bool bonly, const PatchWarm* warm, int warm_count, hipStream_t st) {
     const int cx = count_parity(n, colour & 1), cy = count_parity(n, (colour >> 1) & 1),
               cz = count_parity(n, (colour >> 2) & 1);
     const int grid = warm ? warm_count : cx * cy * cz;
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((patch_solve_kernel<K, T, NTP>), dim3(grid), dim3(PatchShape<K, NTP>::NT), 0, st,
+    hipLaunchKernelGGL((patch_solve_kernel<K, T, NTP, MF>), dim3(grid), dim3(PatchShape<K, NTP>::NT), 0, st,
                        static_cast<T*>(x),
                        static_cast<const T*>(r), static_cast<const T*>(ptab), n, colour, cx, cy, T(rtol), maxit,
                        counters, int(bonly), warm ? *warm : PatchWarm{});
@@ -59,6 +59,16 @@ hipError_t launch_patch_solve(int k, bool f64, void* x, const void* r, const voi
                               double cg_rtol, int cg_max_it, unsigned long long* counters, bool boundary_only, hipStream_t st) {
     return f64 ? launch_k<double>(k, x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st, nullptr, 0)
                : launch_k<float>(k, x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, boundary_only, st, nullptr, 0);
+}
+
+hipError_t launch_patch_solve_mf(int k, void* x, const void* r, const void* ptab, int n, int colour, double cg_rtol,
+                                 int cg_max_it, unsigned long long* counters, hipStream_t st) {
+    switch (k) {
+        case 1: return launch_nt<1, float, 0, true>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, false, nullptr, 0, st);
+        case 2: return launch_nt<2, float, 0, true>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, false, nullptr, 0, st);
+        case 3: return launch_nt<3, float, 0, true>(x, r, ptab, n, colour, cg_rtol, cg_max_it, counters, false, nullptr, 0, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_patch_solve_warm(int k, bool f64, void* x, const void* r, const void* ptab, int n, int colour,

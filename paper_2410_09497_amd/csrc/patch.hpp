@@ -11,6 +11,11 @@ namespace smg {
 hipError_t launch_patch_solve(int k, bool f64, void* x, const void* r, const void* ptab, int n, int colour,
                               double cg_rtol, int cg_max_it, unsigned long long* counters, bool boundary_only, hipStream_t st);
 
+// launch_patch_solve for an FP32 level (degrees 1..3) with the in-plane eigenbasis products of the fast
+// diagonalization on the matrix cores (BF16 operands, FP32 accumulation); every patch of the colour.
+hipError_t launch_patch_solve_mf(int k, void* x, const void* r, const void* ptab, int n, int colour, double cg_rtol,
+                                 int cg_max_it, unsigned long long* counters, hipStream_t st);
+
 // The interior patches p0 .. p0 + count - 1 of colour `colour` (the order of the network's batches), each
 // Schur CG started from the pressure the network predicted: y rows hold (U, h P) / s, s the input scales
 // (float, from the MLP workspace).  Same tolerance test as the cold start (relative to the cold-start

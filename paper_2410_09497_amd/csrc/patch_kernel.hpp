@@ -180,6 +180,101 @@ __device__ inline void fd_inverse(T* v, T* w, const T* const* Sdir, const T* con
     __syncthreads();
 }
 
+// ---- in-plane eigenbasis products on the matrix cores (FP32 cycle, BF16 operands)
+//
+// For velocity component c with extents (e0, e1, e2), the first two factors of
+// the fast diagonalization form one matrix Q_c = S_0 (x) S_1 of order e0 e1,
+// Q_c[j][m] = S_0[i0][i0'] S_1[i1][i1'] for j = i0 + e0 i1, m = i0' + e0 i1'.
+// The in-plane products of every z-slice of the component are then one GEMM:
+// forward  W[z][m] = sum_j V[z][j] Q_c[j][m],  back  V[z][j] = sum_m W[z][m] Q_c[j][m],
+// on v_mfma_f32_16x16x16_bf16 (operands rounded to BF16, FP32 accumulation),
+// the z-slices (e2 <= 8) as the rows of one 16-row block.  Q_c sits in LDS in
+// BF16, padded with zeros to KP x KP.  The z factor and the eigenvalue scaling
+// stay on the vector units.
+template <int K>
+struct MfShape {
+    static constexpr int ND = 2 * K + 2;
+    static constexpr int KP = (ND * ND + 15) / 16 * 16;   // padded order of Q_c
+};
+
+typedef short bf16x4_bits __attribute__((ext_vector_type(4)));
+typedef float f32x4_mf __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_bits(float f) { return __builtin_bit_cast(short, __bf16(f)); }
+
+// Q_c for the three components into Qm (3 KP x KP, BF16 bits, row j = input index)
+template <int K, int NTP>
+__device__ inline void build_inplane(short* Qm, const float* const* Sdir) {
+    using P = PatchShape<K, NTP>;
+    constexpr int KP = MfShape<K>::KP;
+    for (int i = threadIdx.x; i < 3 * KP * KP; i += P::NT) {
+        const int c = i / (KP * KP), jm = i - c * KP * KP, j = jm / KP, m = jm - j * KP;
+        const int e0 = ext<K>(c, 0), e1 = ext<K>(c, 1);
+        float v = 0.0f;
+        if (j < e0 * e1 && m < e0 * e1) {
+            const int i0 = j % e0, i1 = j / e0, o0 = m % e0, o1 = m / e0;
+            v = Sdir[c * 3 + 0][i0 * e0 + o0] * Sdir[c * 3 + 1][i1 * e1 + o1];
+        }
+        Qm[i] = bf16_bits(v);
+    }
+}
+
+// out_c = in_c Q_c (FWD) or in_c Q_c^T (back) for the three components, z-slices as rows
+template <int K, int NTP, bool FWD>
+__device__ inline void inplane_mfma(const float* in, float* out, const short* Qm) {
+    using P = PatchShape<K, NTP>;
+    constexpr int NV = P::NV, KP = MfShape<K>::KP, NB = KP / 16;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int fr = lane & 15, fq = lane >> 4;
+    for (int tile = w; tile < 3 * NB; tile += P::NW) {
+        const int c = tile / NB, nb = tile - c * NB;
+        const int e0 = ext<K>(c, 0), e1 = ext<K>(c, 1), e2 = ext<K>(c, 2), pl = e0 * e1;
+        const float* src = in + c * NV;
+        const short* Q = Qm + c * KP * KP;
+        f32x4_mf acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < NB; ++ks) {
+            const int k0 = ks * 16 + 4 * fq;
+            bf16x4_bits a, b;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int kk = k0 + t;
+                a[t] = bf16_bits((fr < e2 && kk < pl) ? src[fr * pl + kk] : 0.0f);
+                // B[k][col]: forward Q[k][col], back Q[col][k]
+                b[t] = FWD ? Q[kk * KP + nb * 16 + fr] : Q[(nb * 16 + fr) * KP + kk];
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+        const int col = nb * 16 + fr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int z = 4 * fq + e;
+            if (z < e2 && col < pl) out[c * NV + z * pl + col] = acc[e];
+        }
+    }
+}
+
+// v <- A^{-1} v (FP32) with the in-plane factors on the matrix cores, work buffer w
+template <int K, int NTP>
+__device__ inline void fd_inverse_mf(float* v, float* w, const float* const* Sdir, const float* const* Ldir,
+                                     const int* codes, const short* Qm) {
+    using P = PatchShape<K, NTP>;
+    constexpr int NV = P::NV;
+    inplane_mfma<K, NTP, true>(v, w, Qm);
+    __syncthreads();
+    contract3<K, NTP, float, true, 2>(w, v, Sdir, codes);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
+        const int code = codes[idx], c = code_c(code);
+        v[idx] /= Ldir[c * 3 + 0][code_i(code, 0)] + Ldir[c * 3 + 1][code_i(code, 1)] + Ldir[c * 3 + 2][code_i(code, 2)];
+    }
+    __syncthreads();
+    contract3<K, NTP, float, false, 2>(v, w, Sdir, codes);
+    __syncthreads();
+    inplane_mfma<K, NTP, false>(w, v, Qm);
+    __syncthreads();
+}
+
 // vel = B^T p:  (B^T p)_c[i] = -D^T along c times the DG masses of the other directions
 template <int K, int NTP, typename T>
 __device__ inline void apply_BT(const T* p, T* vel, const T* Dp, const T* md, const int* codes) {
@@ -266,7 +361,7 @@ struct PatchWarm {
     int cnt[3] = {0, 0, 0};   // interior vertices per direction of the colour
 };
 
-template <int K, typename T, int NTP = 0>
+template <int K, typename T, int NTP = 0, bool MF = false>
 __global__ void __launch_bounds__((PatchShape<K, NTP>::NT))
 patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restrict__ tab, int n, int colour,
                    int cntx, int cnty, T cg_rtol, int cg_maxit, unsigned long long* __restrict__ counters, int boundary_only,
@@ -279,6 +374,8 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     __shared__ T Pv[NP], R[NP], Dv[NP], Q[NP];
     __shared__ T red[2 * NW];
     __shared__ int codes[3 * NV];
+    static_assert(!MF || (sizeof(T) == 4 && K <= 3), "matrix-core eigenbasis products: FP32 cycle, degrees 1..3");
+    __shared__ short Qm[MF ? 3 * MfShape<K>::KP * MfShape<K>::KP : 1];
 
     const int tid = threadIdx.x;
     // vertex of this workgroup: coordinates of parity (colour bit) in 1..n-1
@@ -331,6 +428,16 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     // per component c and direction d: continuous factors on the diagonal
     const T* Sdir[9] = {SC, SDy, SDz, SDx, SC, SDz, SDx, SDy, SC};
     const T* Ldir[9] = {LC, LDy, LDz, LDx, LC, LDz, LDx, LDy, LC};
+    // A^{-1} by fast diagonalization: every product on the vector units, or (MF) the in-plane ones on the
+    // matrix cores
+    auto a_inverse = [&](T* vv, T* ww) {
+        if constexpr (MF) fd_inverse_mf<K, NTP>(vv, ww, Sdir, Ldir, codes, Qm);
+        else fd_inverse<K, NTP, T>(vv, ww, Sdir, Ldir, codes);
+    };
+    if constexpr (MF) {
+        build_inplane<K, NTP>(Qm, Sdir);
+        __syncthreads();
+    }
 
     // G <- G - mean(G)
     {
@@ -340,7 +447,7 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
         for (int i = tid; i < NP; i += P::NT) R[i] -= mean;
     }
     // V1 = A^{-1} F;  rhs = B V1 - G (projected)
-    fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir, codes);
+    a_inverse(V1, W1);
     apply_B<K, NTP, T>(V1, Q, Dp, md);
     __syncthreads();
     T rr;
@@ -378,7 +485,7 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
         __syncthreads();
         apply_BT<K, NTP, T>(Pv, V1, Dp, md, codes);
         __syncthreads();
-        fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir, codes);
+        a_inverse(V1, W1);
         apply_B<K, NTP, T>(V1, Q, Dp, md);
         __syncthreads();
         T sq = 0;
@@ -402,7 +509,7 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
         // Q = S Dv = B A^{-1} B^T Dv, projected to mean zero
         apply_BT<K, NTP, T>(Dv, V1, Dp, md, codes);
         __syncthreads();
-        fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir, codes);
+        a_inverse(V1, W1);
         apply_B<K, NTP, T>(V1, Q, Dp, md);
         __syncthreads();
         T s = 0, dq = 0;
@@ -446,7 +553,7 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
         V1[i] = r[gi.template vel<K>(c, i - c * NV)] - V1[i];
     }
     __syncthreads();
-    fd_inverse<K, NTP, T>(V1, W1, Sdir, Ldir, codes);
+    a_inverse(V1, W1);
     // scatter x += R_j^T (U, P); the DoF sets of one colour are disjoint
     for (int i = tid; i < 3 * NV; i += P::NT) {
         const int c = i / NV;

@@ -7,8 +7,9 @@ outcome, one JSON line per solve:
 u = curl(sin(pi x) sin(pi y) sin(pi z) (1,1,1)), p = cos(pi x) cos(pi y) cos(pi z);
 FGMRES(restart) preconditioned by the V-cycle down to 1^3 cells.  --local
 lists the local solvers to run one after the other: exact (Schur CG
-everywhere) and direct (interior patches by the Direct solver on the matrix
-cores, BF16 operands unless --operands f32).  L2 errors of every solution
+everywhere), exact_bf16 (the Schur CG with its in-plane eigenbasis products
+on the matrix cores, FP32 cycle) and direct (every patch by the Direct solver
+on the matrix cores, BF16 operands unless --operands f32).  L2 errors of every solution
 are printed too."""
 import argparse
 import json
@@ -28,7 +29,7 @@ def main():
     ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--cg-rtol", type=float, default=1e-3)
     ap.add_argument("--cg-max-it", type=int, default=15)
-    ap.add_argument("--local", nargs="+", choices=["exact", "direct"], default=["exact"])
+    ap.add_argument("--local", nargs="+", choices=["exact", "exact_bf16", "direct"], default=["exact"])
     ap.add_argument("--operands", choices=["bf16", "f32"], default="bf16")
     args = ap.parse_args()
     from paper_2410_09497_amd import StokesMG
@@ -42,7 +43,8 @@ def main():
         x, info = mg.solve(b, rtol=args.rtol, restart=args.restart, vcycle_dtype=args.vcycle)
         eu, ep = mg.l2_error(x)
         print(json.dumps({"n": args.n, "k": args.k, "vcycle": args.vcycle, "local_solver": local,
-                          "operands": args.operands if local != "exact" else None, "unknowns": mg.ndof(),
+                          "operands": args.operands if local == "direct" else ("bf16" if local == "exact_bf16" else None),
+                          "unknowns": mg.ndof(),
                           "iterations": info["iterations"], "seconds": info["seconds"],
                           "rel_residual": info["rel_residual"], "nu": info["nu"], "l2_error_u": eu,
                           "l2_error_p": ep}), flush=True)
