@@ -125,7 +125,7 @@ __device__ inline void block_sum2(T& a, T& b, T* red) {
 // one entry of contract3 for component C along direction D: every stride is a
 // compile-time constant, so the LDS reads use immediate offsets
 template <int K, typename T, bool TR, int C, int D>
-__device__ inline T contract_entry(const T* in, int idx, int ii, const T* S) {
+__device__ __forceinline__ T contract_entry(const T* in, int idx, int ii, const T* S) {
     constexpr int NC = 2 * K + 1, ND = 2 * K + 2;
     constexpr int e0 = C == 0 ? NC : ND, e1 = C == 1 ? NC : ND;
     constexpr int st = D == 0 ? 1 : (D == 1 ? e0 : e0 * e1);
@@ -139,7 +139,7 @@ __device__ inline T contract_entry(const T* in, int idx, int ii, const T* S) {
 }
 
 template <int K, int NTP, typename T, bool TR, int D>
-__device__ inline void contract3(const T* in, T* out, const T* const* Sdir, const int* codes) {
+__device__ __forceinline__ void contract3(const T* in, T* out, const T* const* Sdir, const int* codes) {
     using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV;
     for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
@@ -156,7 +156,7 @@ __device__ inline void contract3(const T* in, T* out, const T* const* Sdir, cons
 
 // v <- A^{-1} v for the three components (in place), work buffer w
 template <int K, int NTP, typename T>
-__device__ inline void fd_inverse(T* v, T* w, const T* const* Sdir, const T* const* Ldir, const int* codes) {
+__device__ __forceinline__ void fd_inverse(T* v, T* w, const T* const* Sdir, const T* const* Ldir, const int* codes) {
     using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV;
     // a thread per entry: lanes read with unit stride (a thread per 1D line reads
@@ -221,7 +221,7 @@ __device__ inline void build_inplane(short* Qm, const float* const* Sdir) {
 
 // out_c = in_c Q_c (FWD) or in_c Q_c^T (back) for the three components, z-slices as rows
 template <int K, int NTP, bool FWD>
-__device__ inline void inplane_mfma(const float* in, float* out, const short* Qm) {
+__device__ __forceinline__ void inplane_mfma(const float* in, float* out, const short* Qm) {
     using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV, KP = MfShape<K>::KP, NB = KP / 16;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -256,7 +256,7 @@ __device__ inline void inplane_mfma(const float* in, float* out, const short* Qm
 
 // v <- A^{-1} v (FP32) with the in-plane factors on the matrix cores, work buffer w
 template <int K, int NTP>
-__device__ inline void fd_inverse_mf(float* v, float* w, const float* const* Sdir, const float* const* Ldir,
+__device__ __forceinline__ void fd_inverse_mf(float* v, float* w, const float* const* Sdir, const float* const* Ldir,
                                      const int* codes, const short* Qm) {
     using P = PatchShape<K, NTP>;
     constexpr int NV = P::NV;
@@ -429,8 +429,8 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     const T* Sdir[9] = {SC, SDy, SDz, SDx, SC, SDz, SDx, SDy, SC};
     const T* Ldir[9] = {LC, LDy, LDz, LDx, LC, LDz, LDx, LDy, LC};
     // A^{-1} by fast diagonalization: every product on the vector units, or (MF) the in-plane ones on the
-    // matrix cores
-    auto a_inverse = [&](T* vv, T* ww) {
+    // matrix cores (inlined: the LDS arrays keep their address space)
+    auto a_inverse = [&](T* vv, T* ww) __attribute__((always_inline)) {
         if constexpr (MF) fd_inverse_mf<K, NTP>(vv, ww, Sdir, Ldir, codes, Qm);
         else fd_inverse<K, NTP, T>(vv, ww, Sdir, Ldir, codes);
     };
