@@ -278,8 +278,9 @@ int stokesmg_rhs_fourier(stokesmg_t* h, int level, int n_modes, const int* kappa
 int mlp_dims(const stokesmg_t* h, int64_t* d, int64_t* n_params);
 
 /* Bytes of the MLP workspace for batches of up to max_rows rows (training
- * batches, or the patches of one colour per chunk in the smoother); for
- * degrees 1..3 it includes the Direct solver's 28 d x d FP32 matrices. */
+ * batches, or the interior patches of one colour per chunk in the learned
+ * smoother); for degrees 1..3 it includes the Direct solver's 28 maps, padded
+ * to whole tiles, in FP32 and in BF16 (99 MB at k = 2, 718 MB at k = 3). */
 int mlp_workspace_size(const stokesmg_t* h, int64_t max_rows, size_t* bytes);
 int mlp_set_workspace(stokesmg_t* h, void* dev_ptr, size_t bytes, int64_t max_rows);
 
@@ -340,8 +341,9 @@ int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode, dou
  * stokesmg_direct_matrix writes the matrix of one type to host memory (d x d
  * doubles, row-major [out][in], d from mlp_dims; no device needed; EINVAL
  * for a type outside 0..27).  stokesmg_direct_setup builds all 28 (on host
- * threads) and uploads them (FP32) into the MLP workspace, which must be set
- * (ENOMEM); synchronizes `stream`.  Degrees 1..3 (EUNSUPPORTED). */
+ * threads) and uploads them, padded to whole tiles, in FP32 and rounded to
+ * BF16 (nearest even) into the MLP workspace, which must be set (ENOMEM);
+ * synchronizes `stream`.  Degrees 1..3 (EUNSUPPORTED). */
 int stokesmg_direct_matrix(const stokesmg_t* h, int type, double* M);
 int stokesmg_direct_setup(stokesmg_t* h, void* stream);
 
