@@ -347,6 +347,15 @@ int stokesmg_set_local_solver(stokesmg_t* h, int local_solver, int mlp_mode, dou
 int stokesmg_direct_matrix(const stokesmg_t* h, int type, double* M);
 int stokesmg_direct_setup(stokesmg_t* h, void* stream);
 
+/* Smoothing sweeps of the V-cycle (vcycle, solve, mlp_collect_pairs): pre
+ * sweeps before the coarse-grid correction (the first from x = 0) and post
+ * sweeps after it, each one patch_smooth sweep over the 8 colours in
+ * ascending order.  Default 1 / 1, the single pre- and post-smoothing step of
+ * Sec. 3; the iteration counts the paper prints (Table 1 in 2D, at most three
+ * steps from k = 3 in 3D, Sec. 3.3) are met with 2 / 2 in this
+ * implementation.  0..16 each, at least one in total (EINVAL). */
+int stokesmg_set_smoothing(stokesmg_t* h, int pre_sweeps, int post_sweeps);
+
 /* Fallback of the learned solver inside solve(): with the MLP local solver,
  * after FGMRES step j with contraction rho_j = res_j / res_{j-1} of the
  * residual estimate, the rest of the solve uses the exact local solver when

@@ -336,3 +336,7 @@ class StokesMG:
 
     def set_fallback(self, rho_ref):
         self._check(_lib.lib.stokesmg_set_fallback(self._h, float(rho_ref)))
+
+    def set_smoothing(self, pre=1, post=1):
+        """Smoothing sweeps of the V-cycle before and after the coarse correction."""
+        self._check(_lib.lib.stokesmg_set_smoothing(self._h, int(pre), int(post)))

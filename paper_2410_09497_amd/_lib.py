@@ -72,6 +72,7 @@ def _load():
                             ctypes.POINTER(ctypes.c_float), vp]),
         "stokesmg_set_local_solver": (i32, [vp, i32, i32, ctypes.c_double]),
         "stokesmg_set_fallback": (i32, [vp, ctypes.c_double]),
+        "stokesmg_set_smoothing": (i32, [vp, i32, i32]),
         "stokesmg_direct_matrix": (i32, [vp, i32, vp]),
         "stokesmg_l2_error": (i32, [vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                     vp]),
@@ -91,4 +92,4 @@ EXPORTED = ["stokesmg_create", "stokesmg_destroy", "stokesmg_last_error", "stoke
             "stokes_residual", "patch_smooth", "stokesmg_cg_stats", "vcycle", "stokesmg_solve_workspace_size",
             "solve", "stokesmg_rhs_manufactured", "stokesmg_rhs_fourier", "mlp_dims", "mlp_workspace_size", "mlp_set_workspace", "mlp_init",
             "mlp_get_state", "mlp_set_state", "mlp_forward", "mlp_backward", "mlp_adam_step", "mlp_collect_pairs",
-            "mlp_train", "stokesmg_set_local_solver", "stokesmg_set_fallback"]
+            "mlp_train", "stokesmg_set_local_solver", "stokesmg_set_fallback", "stokesmg_set_smoothing"]

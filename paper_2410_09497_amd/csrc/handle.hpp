@@ -62,6 +62,7 @@ struct stokesmg {
         bool ready = false;        // parameters initialized or set
     } mlp;
     int local_solver = STOKESMG_LOCAL_EXACT;
+    int pre_sweeps = 1, post_sweeps = 1;     // smoothing sweeps of the V-cycle before / after the coarse correction
     int mlp_mode = STOKESMG_MLP_BF16;
     double mlp_omega = 1.0;                  // damping of the learned corrections
     double rho_ref = 0.0;

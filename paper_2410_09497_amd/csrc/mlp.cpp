@@ -519,6 +519,15 @@ int stokesmg_direct_setup(stokesmg_t* h, void* stream) {
     return STOKESMG_OK;
 }
 
+int stokesmg_set_smoothing(stokesmg_t* h, int pre_sweeps, int post_sweeps) {
+    if (!h) return STOKESMG_EINVAL;
+    if (pre_sweeps < 0 || post_sweeps < 0 || pre_sweeps > 16 || post_sweeps > 16 || pre_sweeps + post_sweeps < 1)
+        return h->fail(STOKESMG_EINVAL, "sweeps must be in 0..16, at least one in total");
+    h->pre_sweeps = pre_sweeps;
+    h->post_sweeps = post_sweeps;
+    return STOKESMG_OK;
+}
+
 int stokesmg_set_fallback(stokesmg_t* h, double rho_ref) {
     if (!h) return STOKESMG_EINVAL;
     h->rho_ref = rho_ref;

@@ -33,7 +33,8 @@ int vcycle_level(stokesmg* h, int l, bool f64, const void* b, void* x, hipStream
     const smg::Capture* lc = (l == h->n_levels - 1) ? cap : nullptr;
     // pre-smoothing from x = 0
     SMG_HIP(h, smg::launch_zero(f64, x, N, st));
-    if (int rc = smg::smooth_sweep(h, l, f64, x, b, st, lc)) return rc;
+    for (int s = 0; s < h->pre_sweeps; ++s)
+        if (int rc = smg::smooth_sweep(h, l, f64, x, b, st, lc)) return rc;
     // coarse-grid correction: b_{l-1} = P^T (b - K x), x += P P_{l-1}^{-1} b_{l-1}
     SMG_HIP(h, smg::launch_apply(k, f64, true, x, b, r, tab, n, st));
     const auto& o = h->tro[l];
@@ -51,7 +52,9 @@ int vcycle_level(stokesmg* h, int l, bool f64, const void* b, void* x, hipStream
                                     reinterpret_cast<const int*>(w + o.pc_i),
                                     reinterpret_cast<const double*>(w + o.pc_w), o.wpc, w + h->c_vec, st));
     // post-smoothing
-    return smg::smooth_sweep(h, l, f64, x, b, st, lc);
+    for (int s = 0; s < h->post_sweeps; ++s)
+        if (int rc = smg::smooth_sweep(h, l, f64, x, b, st, lc)) return rc;
+    return STOKESMG_OK;
 }
 
 int check_mg(stokesmg* h) {
