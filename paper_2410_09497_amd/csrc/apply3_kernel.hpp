@@ -33,10 +33,18 @@ struct SplitShape {
     static constexpr int NL = (RS + NT - 1) / NT;       // plane elements per thread and field
 };
 
-template <int K, typename T, int CX, int CY, bool RESID, int ROLE>
+// GT: the group's in-plane stencil rows (which differ from lane to lane) are
+// read from global memory through the vector cache instead of from LDS.  The
+// z rows are the same for every lane of a plane and are always read from
+// global memory, which makes them scalar loads.  Splitting the reads between
+// the LDS and the vector-memory pipe by group balances the two (measured).
+// HOLD (group A only): its six in-plane rows (Lc, D^T and Ld in x and y) are
+// loaded once into registers and no table is read in the plane loop.
+template <int K, typename T, int CX, int CY, bool RESID, int ROLE, bool GT, bool HOLD = false>
 __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__ bvec, T* __restrict__ y,
-                                  const T* __restrict__ s_tab, T (*s_u)[4][SplitShape<K, CX, CY>::RS], T* s_vx,
-                                  T* s_vy, int n, int L0, int L1, int X0, int Y0) {
+                                  const T* __restrict__ s_tab, const T* __restrict__ g_tab,
+                                  T (*s_u)[4][SplitShape<K, CX, CY>::RS], T* s_vx, T* s_vy, int n, int L0, int L1,
+                                  int X0, int Y0) {
     using S = SplitShape<K, CX, CY>;
     constexpr int M = S::M, TX = S::TX, TY = S::TY, NP = S::NP, NA = S::NA, NT = S::NT, RX = S::RX, RY = S::RY,
                   RS = S::RS, NL = S::NL;
@@ -55,14 +63,40 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
     const T* __restrict__ gz = x + 2 * nc;
     const T* __restrict__ gp = x + 3 * nc;
     const T mda = s_tab[TB::MDg + a], mdb = s_tab[TB::MDg + b];
-    // The stencil rows are re-read from LDS where they are used: the table
-    // base goes through an SGPR move the compiler cannot see through, so the
-    // per-thread rows are not hoisted out of the layer loop into registers.
+    // The stencil rows are re-read where they are used: the table base goes
+    // through an SGPR move the compiler cannot see through, so the rows are
+    // not hoisted out of the layer loop into registers.
     auto tables = [&]() {
         int z;
         asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-        return s_tab + z;
+        return (GT ? g_tab : s_tab) + z;
     };
+    auto ztables = [&]() {
+        int z;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+        return g_tab + z;
+    };
+    static_assert(!HOLD || ROLE == 0, "only group A holds its rows");
+    constexpr int HW = HOLD ? 1 : 0;
+    T hlca[HW * (2 * M + 1) + 1], hlcb[HW * (2 * M + 1) + 1], hdta[HW * 2 * M + 1], hdtb[HW * 2 * M + 1],
+        hlda[HW * 3 * M + 1], hldb[HW * 3 * M + 1];
+    if constexpr (HOLD) {
+#pragma unroll
+        for (int o = 0; o < 2 * M + 1; ++o) {
+            hlca[o] = g_tab[TB::LC + a * (2 * M + 1) + o];
+            hlcb[o] = g_tab[TB::LC + b * (2 * M + 1) + o];
+        }
+#pragma unroll
+        for (int o = 0; o < 2 * M; ++o) {
+            hdta[o] = g_tab[TB::DT + a * 2 * M + o];
+            hdtb[o] = g_tab[TB::DT + b * 2 * M + o];
+        }
+#pragma unroll
+        for (int o = 0; o < 3 * M; ++o) {
+            hlda[o] = g_tab[TB::LD + vxv * 3 * M * M + a * 3 * M + o];
+            hldb[o] = g_tab[TB::LD + vyv * 3 * M * M + b * 3 * M + o];
+        }
+    }
 
     // plane Z of the four fields, tile + halo, zero outside the domain (all threads share the loads)
     auto load_plane = [&](int Z, T (&v)[4][NL]) {
@@ -163,13 +197,17 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
                     const T* rux = sux + ry * RX;
 #pragma unroll
                     for (int o = 0; o < 2 * M + 1; ++o) {
-                        lcx += LC[a * (2 * M + 1) + o] * rux[rx + o - M];
-                        lcy += LC[b * (2 * M + 1) + o] * suy[(ry + o - M) * RX + rx];
+                        const T ca = HOLD ? hlca[o * HW] : LC[a * (2 * M + 1) + o];
+                        const T cb = HOLD ? hlcb[o * HW] : LC[b * (2 * M + 1) + o];
+                        lcx += ca * rux[rx + o - M];
+                        lcy += cb * suy[(ry + o - M) * RX + rx];
                     }
 #pragma unroll
                     for (int o = 0; o < 2 * M; ++o) {
-                        dtx += DT[a * 2 * M + o] * sp[ry * RX + tx - a + M + o];
-                        dty += DT[b * 2 * M + o] * sp[(ty - b + M + o) * RX + rx];
+                        const T ca = HOLD ? hdta[o * HW] : DT[a * 2 * M + o];
+                        const T cb = HOLD ? hdtb[o * HW] : DT[b * 2 * M + o];
+                        dtx += ca * sp[ry * RX + tx - a + M + o];
+                        dty += cb * sp[(ty - b + M + o) * RX + rx];
                     }
                 }
                 __syncthreads();
@@ -179,8 +217,10 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
                         T ldyvx = 0, ldxvy = 0;
 #pragma unroll
                         for (int o = 0; o < 3 * M; ++o) {
-                            ldyvx += LD[vyv * 3 * M * M + b * 3 * M + o] * s_vx[(ty - b + o) * TX + tx];
-                            ldxvy += LD[vxv * 3 * M * M + a * 3 * M + o] * s_vy[ty * RX + tx - a + o];
+                            const T cb = HOLD ? hldb[o * HW] : LD[vyv * 3 * M * M + b * 3 * M + o];
+                            const T ca = HOLD ? hlda[o * HW] : LD[vxv * 3 * M * M + a * 3 * M + o];
+                            ldyvx += cb * s_vx[(ty - b + o) * TX + tx];
+                            ldxvy += ca * s_vy[ty * RX + tx - a + o];
                         }
                         r0 = mdb * mdc * (lcx - dtx) + mdc * ldyvx;   // in-plane part of y_x
                         r1 = mda * mdc * (lcy - dty) + mdc * ldxvy;   // in-plane part of y_y
@@ -225,7 +265,7 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
         const int L = Lin - 1;
         if (L >= L0) {
             const bool okxy = act && X < N1 && Y < N1;
-            const T* tb = tables();
+            const T* tb = ztables();
             const T* __restrict__ MC = tb + TB::MC;
             const T* __restrict__ LC = tb + TB::LC;
             const T* __restrict__ DT = tb + TB::DT;
@@ -286,7 +326,7 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
     }
 }
 
-template <int K, typename T, int CX, int CY, bool RESID>
+template <int K, typename T, int CX, int CY, bool RESID, bool GA, bool GB, bool HA>
 __global__ void __launch_bounds__((SplitShape<K, CX, CY>::NT))
 stokes_apply_split_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T* __restrict__ y,
                           const T* __restrict__ tab, int n, int cz, int tiles_x, int tiles_y) {
@@ -308,9 +348,9 @@ stokes_apply_split_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T
     __syncthreads();
     // the groups are whole waves; each runs its copy of the layer loop (same barriers, same order)
     if (threadIdx.x < S::NA)
-        split_loop<K, T, CX, CY, RESID, 0>(x, bvec, y, s_tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
+        split_loop<K, T, CX, CY, RESID, 0, GA, HA>(x, bvec, y, s_tab, tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
     else
-        split_loop<K, T, CX, CY, RESID, 1>(x, bvec, y, s_tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
+        split_loop<K, T, CX, CY, RESID, 1, GB>(x, bvec, y, s_tab, tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
 }
 
 }  // namespace smg
