@@ -7,11 +7,16 @@
 // on Mc_x u_x and Mc_y u_y from its register windows.  Group B owns y_z and
 // y_p: the in-plane Ld rows on u_z, the divergence rows D u, and the z
 // stencils Mc_z, Lc_z, D^T_z, D_z from its windows; it also forms the shared
-// Mc_x u_x / Mc_y u_y planes while group A evaluates its first in-plane
-// terms.  Each group runs its own copy of the layer loop, so a thread keeps
-// only its group's windows live (about half the registers of one thread per
-// position), and a CU holds twice as many waves.  Both copies pass the same
-// barriers in the same order.
+// Mc_x u_x plane (and the Mc_y u_y plane, unless group A forms it first: AVY)
+// while group A evaluates its first in-plane terms.  Each group runs its own
+// copy of the layer loop, so a thread keeps only its group's windows live
+// (about half the registers of one thread per position), and a CU holds twice
+// as many waves.  Both copies pass the same barriers in the same order.
+//
+// The kernel is bound by LDS issue, so the per-degree options (apply_launch.hpp)
+// move work off LDS: the z rows are scalar loads, each group's in-plane rows
+// sit in registers, LDS or the vector cache, and the two groups' LDS reads
+// are evened out.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,7 +26,7 @@
 
 namespace smg {
 
-template <int K, int CX, int CY>
+template <int K, int CX, int CY, bool PAD = false>
 struct SplitShape {
     static constexpr int M = K + 1;
     static constexpr int TX = CX * M, TY = CY * M;
@@ -31,6 +36,11 @@ struct SplitShape {
     static constexpr int RX = TX + 2 * M, RY = TY + 2 * M;
     static constexpr int RS = RX * RY;
     static constexpr int NL = (RS + NT - 1) / NT;       // plane elements per thread and field
+    // LDS row pitch of the planes and of Mc_y u_y; PAD: congruent to the tile
+    // width modulo 16 elements, so the 16 lanes of one LDS cycle that straddle a
+    // tile row end still hit distinct banks (pays only for FP64 at degree 2)
+    static constexpr int PX = PAD ? RX + ((TX - RX) % 16 + 16) % 16 : RX;
+    static constexpr int PS = PX * RY;
 };
 
 // GT: the group's in-plane stencil rows (which differ from lane to lane) are
@@ -38,16 +48,19 @@ struct SplitShape {
 // z rows are the same for every lane of a plane and are always read from
 // global memory, which makes them scalar loads.  Splitting the reads between
 // the LDS and the vector-memory pipe by group balances the two (measured).
-// HOLD (group A only): its six in-plane rows (Lc, D^T and Ld in x and y) are
-// loaded once into registers and no table is read in the plane loop.
-template <int K, typename T, int CX, int CY, bool RESID, int ROLE, bool GT, bool HOLD = false>
+// HOLD: the group's rows that do not change along the plane loop are loaded
+// once into registers (group A: Lc, D^T and Ld in x and y; group B: Ld and D
+// in x and y).
+// AVY: group A forms the Mc_y u_y plane (before its own first rows) and group
+// B only the Mc_x u_x plane, which evens out their LDS reads.
+template <int K, typename T, int CX, int CY, bool RESID, int ROLE, bool GT, bool HOLD, bool AVY, bool PAD>
 __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__ bvec, T* __restrict__ y,
                                   const T* __restrict__ s_tab, const T* __restrict__ g_tab,
-                                  T (*s_u)[4][SplitShape<K, CX, CY>::RS], T* s_vx, T* s_vy, int n, int L0, int L1,
+                                  T (*s_u)[4][SplitShape<K, CX, CY, PAD>::PS], T* s_vx, T* s_vy, int n, int L0, int L1,
                                   int X0, int Y0) {
-    using S = SplitShape<K, CX, CY>;
+    using S = SplitShape<K, CX, CY, PAD>;
     constexpr int M = S::M, TX = S::TX, TY = S::TY, NP = S::NP, NA = S::NA, NT = S::NT, RX = S::RX, RY = S::RY,
-                  RS = S::RS, NL = S::NL;
+                  RS = S::RS, NL = S::NL, PX = S::PX, PS = S::PS;
     using TB = Tab<K>;
     const int tid = threadIdx.x;
     const int p = tid - ROLE * NA;                 // position of this thread in its group
@@ -76,11 +89,10 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
         asm volatile("s_mov_b32 %0, 0" : "=s"(z));
         return g_tab + z;
     };
-    static_assert(!HOLD || ROLE == 0, "only group A holds its rows");
     constexpr int HW = HOLD ? 1 : 0;
     T hlca[HW * (2 * M + 1) + 1], hlcb[HW * (2 * M + 1) + 1], hdta[HW * 2 * M + 1], hdtb[HW * 2 * M + 1],
         hlda[HW * 3 * M + 1], hldb[HW * 3 * M + 1];
-    if constexpr (HOLD) {
+    if constexpr (HOLD && ROLE == 0) {
 #pragma unroll
         for (int o = 0; o < 2 * M + 1; ++o) {
             hlca[o] = g_tab[TB::LC + a * (2 * M + 1) + o];
@@ -91,10 +103,21 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
             hdta[o] = g_tab[TB::DT + a * 2 * M + o];
             hdtb[o] = g_tab[TB::DT + b * 2 * M + o];
         }
+    }
+    if constexpr (HOLD) {
 #pragma unroll
         for (int o = 0; o < 3 * M; ++o) {
             hlda[o] = g_tab[TB::LD + vxv * 3 * M * M + a * 3 * M + o];
             hldb[o] = g_tab[TB::LD + vyv * 3 * M * M + b * 3 * M + o];
+        }
+    }
+    constexpr int HB = (HOLD && ROLE == 1) ? 1 : 0;
+    T hdda[HB * (M + 1) + 1], hddb[HB * (M + 1) + 1];
+    if constexpr (HB) {
+#pragma unroll
+        for (int j = 0; j < M + 1; ++j) {
+            hdda[j] = g_tab[TB::DD + a * (M + 1) + j];
+            hddb[j] = g_tab[TB::DD + b * (M + 1) + j];
         }
     }
 
@@ -153,16 +176,17 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
                 for (int t = 0; t < NL; ++t) {
                     const int i = tid + t * NT;
                     if (i < RS) {
+                        const int li = (i / RX) * PX + i % RX;
 #pragma unroll
-                        for (int f = 0; f < 4; ++f) su[f * RS + i] = pf[f][t];
+                        for (int f = 0; f < 4; ++f) su[f * PS + li] = pf[f][t];
                     }
                 }
                 if (Z < Zlast) load_plane(Z + 1, pf);
                 __syncthreads();
                 const T* sux = su;
-                const T* suy = su + RS;
-                const T* suz = su + 2 * RS;
-                const T* sp = su + 3 * RS;
+                const T* suy = su + PS;
+                const T* suz = su + 2 * PS;
+                const T* sp = su + 3 * PS;
                 const int rx = tx + M, ry = ty + M;
                 const T* tb = tables();
                 const T* __restrict__ MC = tb + TB::MC;
@@ -173,41 +197,45 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
                 const T mdc = tb[TB::MDg + c];
                 T lcx = 0, dtx = 0, lcy = 0, dty = 0;
                 if constexpr (ROLE == 1) {
-                    // 2B) Mc along x for the rows the y stencil needs, Mc along y for the columns
+                    // 2B) Mc along x for the rows the y stencil needs (and, unless group A does it,
+                    // Mc along y for the columns the x stencil needs)
                     for (int i = p; i < TX * RY; i += NA) {
                         const int qx = i % TX, qy = i / TX;
                         const T* row = MC + (qx % M) * (2 * M + 1);
-                        const T* src = sux + qy * RX + qx;
+                        const T* src = sux + qy * PX + qx;
                         T acc = 0;
 #pragma unroll
                         for (int o = 0; o < 2 * M + 1; ++o) acc += row[o] * src[o];
                         s_vx[i] = acc;
                     }
+                }
+                if constexpr (ROLE == (AVY ? 0 : 1)) {
                     for (int i = p; i < RX * TY; i += NA) {
                         const int qx = i % RX, qy = i / RX;
                         const T* row = MC + (qy % M) * (2 * M + 1);
-                        const T* src = suy + qy * RX + qx;
+                        const T* src = suy + qy * PX + qx;
                         T acc = 0;
 #pragma unroll
-                        for (int o = 0; o < 2 * M + 1; ++o) acc += row[o] * src[o * RX];
-                        s_vy[i] = acc;
+                        for (int o = 0; o < 2 * M + 1; ++o) acc += row[o] * src[o * PX];
+                        s_vy[qy * PX + qx] = acc;
                     }
-                } else if (act) {
+                }
+                if (ROLE == 0 && act) {
                     // 2A) the in-plane rows that need only the raw plane
-                    const T* rux = sux + ry * RX;
+                    const T* rux = sux + ry * PX;
 #pragma unroll
                     for (int o = 0; o < 2 * M + 1; ++o) {
                         const T ca = HOLD ? hlca[o * HW] : LC[a * (2 * M + 1) + o];
                         const T cb = HOLD ? hlcb[o * HW] : LC[b * (2 * M + 1) + o];
                         lcx += ca * rux[rx + o - M];
-                        lcy += cb * suy[(ry + o - M) * RX + rx];
+                        lcy += cb * suy[(ry + o - M) * PX + rx];
                     }
 #pragma unroll
                     for (int o = 0; o < 2 * M; ++o) {
                         const T ca = HOLD ? hdta[o * HW] : DT[a * 2 * M + o];
                         const T cb = HOLD ? hdtb[o * HW] : DT[b * 2 * M + o];
-                        dtx += ca * sp[ry * RX + tx - a + M + o];
-                        dty += cb * sp[(ty - b + M + o) * RX + rx];
+                        dtx += ca * sp[ry * PX + tx - a + M + o];
+                        dty += cb * sp[(ty - b + M + o) * PX + rx];
                     }
                 }
                 __syncthreads();
@@ -220,28 +248,32 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
                             const T cb = HOLD ? hldb[o * HW] : LD[vyv * 3 * M * M + b * 3 * M + o];
                             const T ca = HOLD ? hlda[o * HW] : LD[vxv * 3 * M * M + a * 3 * M + o];
                             ldyvx += cb * s_vx[(ty - b + o) * TX + tx];
-                            ldxvy += ca * s_vy[ty * RX + tx - a + o];
+                            ldxvy += ca * s_vy[ty * PX + tx - a + o];
                         }
                         r0 = mdb * mdc * (lcx - dtx) + mdc * ldyvx;   // in-plane part of y_x
                         r1 = mda * mdc * (lcy - dty) + mdc * ldxvy;   // in-plane part of y_y
                         r2 = s_vx[ry * TX + tx];                      // Mc_x u_x at this position
-                        r3 = s_vy[ty * RX + rx];                      // Mc_y u_y
+                        r3 = s_vy[ty * PX + rx];                      // Mc_y u_y
                     } else {
                         T ldxuz = 0, ldyuz = 0, dxux = 0, dyuy = 0;
 #pragma unroll
                         for (int o = 0; o < 3 * M; ++o) {
-                            ldxuz += LD[vxv * 3 * M * M + a * 3 * M + o] * suz[ry * RX + tx - a + o];
-                            ldyuz += LD[vyv * 3 * M * M + b * 3 * M + o] * suz[(ty - b + o) * RX + rx];
+                            const T ca = HOLD ? hlda[o * HW] : LD[vxv * 3 * M * M + a * 3 * M + o];
+                            const T cb = HOLD ? hldb[o * HW] : LD[vyv * 3 * M * M + b * 3 * M + o];
+                            ldxuz += ca * suz[ry * PX + tx - a + o];
+                            ldyuz += cb * suz[(ty - b + o) * PX + rx];
                         }
-                        const T* rux = sux + ry * RX;
+                        const T* rux = sux + ry * PX;
 #pragma unroll
                         for (int j = 0; j < M + 1; ++j) {
-                            dxux += DD[a * (M + 1) + j] * rux[tx - a + M + j - 1];
-                            dyuy += DD[b * (M + 1) + j] * suy[(ty - b + M + j - 1) * RX + rx];
+                            const T ca = HB ? hdda[j * HB] : DD[a * (M + 1) + j];
+                            const T cb = HB ? hddb[j * HB] : DD[b * (M + 1) + j];
+                            dxux += ca * rux[tx - a + M + j - 1];
+                            dyuy += cb * suy[(ty - b + M + j - 1) * PX + rx];
                         }
                         r0 = mdb * ldxuz + mda * ldyuz;                // in-plane Ld on u_z
-                        r1 = suz[ry * RX + rx];                        // u_z
-                        r2 = sp[ry * RX + rx];                         // p
+                        r1 = suz[ry * PX + rx];                        // u_z
+                        r2 = sp[ry * PX + rx];                         // p
                         r3 = -mdc * (mdb * dxux + mda * dyuy);         // in-plane part of y_p
                     }
                 }
@@ -326,16 +358,16 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
     }
 }
 
-template <int K, typename T, int CX, int CY, bool RESID, bool GA, bool GB, bool HA>
-__global__ void __launch_bounds__((SplitShape<K, CX, CY>::NT))
+template <int K, typename T, int CX, int CY, bool RESID, bool GA, bool GB, bool HA, bool HB, bool AVY, bool PAD>
+__global__ void __launch_bounds__((SplitShape<K, CX, CY, PAD>::NT))
 stokes_apply_split_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T* __restrict__ y,
                           const T* __restrict__ tab, int n, int cz, int tiles_x, int tiles_y) {
-    using S = SplitShape<K, CX, CY>;
+    using S = SplitShape<K, CX, CY, PAD>;
     using TB = Tab<K>;
     __shared__ T s_tab[TB::size];
-    __shared__ T s_u[2][4][S::RS];        // ux, uy, uz, p planes (double buffered)
+    __shared__ T s_u[2][4][S::PS];        // ux, uy, uz, p planes (double buffered)
     __shared__ T s_vx[S::TX * S::RY];     // Mc_x ux over tile columns x all region rows
-    __shared__ T s_vy[S::RX * S::TY];     // Mc_y uy over all region columns x tile rows
+    __shared__ T s_vy[S::PX * S::TY];     // Mc_y uy over all region columns x tile rows
     for (int i = threadIdx.x; i < TB::size; i += S::NT) s_tab[i] = tab[i];
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
     const int tile_x = lin % tiles_x;
@@ -348,9 +380,9 @@ stokes_apply_split_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T
     __syncthreads();
     // the groups are whole waves; each runs its copy of the layer loop (same barriers, same order)
     if (threadIdx.x < S::NA)
-        split_loop<K, T, CX, CY, RESID, 0, GA, HA>(x, bvec, y, s_tab, tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
+        split_loop<K, T, CX, CY, RESID, 0, GA, HA, AVY, PAD>(x, bvec, y, s_tab, tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
     else
-        split_loop<K, T, CX, CY, RESID, 1, GB>(x, bvec, y, s_tab, tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
+        split_loop<K, T, CX, CY, RESID, 1, GB, HB, AVY, PAD>(x, bvec, y, s_tab, tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
 }
 
 }  // namespace smg

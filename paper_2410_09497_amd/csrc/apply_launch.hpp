@@ -32,29 +32,34 @@ hipError_t launch_generic(const void* x, const void* b, void* y, const void* tab
     return hipGetLastError();
 }
 
-// Where the split kernel's groups take their in-plane stencil rows from (HA:
-// group A holds its rows in registers; GA / GB: the group reads them from
-// global memory, otherwise from LDS).  The fastest of the combinations
-// measured on MI355X at 64^3 cells per degree and precision; holding needs
-// the registers (it spills in FP64 at degrees 3 and 5 and costs occupancy in
-// FP32 at degree 2).
+// Options of the split kernel per degree and precision: where each group
+// takes its in-plane stencil rows from (HA / HB: the group holds the rows that
+// stay fixed along its plane loop in registers; GA / GB: the group reads its
+// rows from global memory, otherwise from LDS), whether group A forms the
+// Mc_y u_y plane (AVY), and the padded LDS pitch (PAD).  The fastest of the
+// combinations measured on MI355X at 64^3 cells; holding needs the registers
+// (group A's rows spill in FP64 at degrees 3 and 5).
 template <int K, typename T> struct SplitTables {
     static constexpr bool f64 = sizeof(T) == 8;
     static constexpr bool HA = f64 ? K == 2 : (K == 3 || K == 5);
     static constexpr bool GA = !f64 && K == 2;
     static constexpr bool GB = f64 ? K == 3 : K == 5;
+    static constexpr bool HB = f64 ? K == 2 : K != 4;
+    static constexpr bool AVY = f64 ? (K == 2 || K == 3) : (K == 3 || K == 5);
+    static constexpr bool PAD = f64 && K == 2;
 };
 
 template <int K, typename T, bool RESID, int CX = TileOf<K>::CX, int CY = TileOf<K>::CY>
 hipError_t launch_split(const void* x, const void* b, void* y, const void* tab, int n, hipStream_t st) {
-    using S = SplitShape<K, CX, CY>;
+    using S = SplitShape<K, CX, CY, SplitTables<K, T>::PAD>;
     const int N1 = n * S::M;
     const int tiles_x = (N1 + S::TX - 1) / S::TX;
     const int tiles_y = (N1 + S::TY - 1) / S::TY;
     const int cz = apply_chunk_layers(K, n, tiles_x * tiles_y);
     const int nzc = (n + cz - 1) / cz;
     hipLaunchKernelGGL((stokes_apply_split_kernel<K, T, CX, CY, RESID, SplitTables<K, T>::GA, SplitTables<K, T>::GB,
-                                                 SplitTables<K, T>::HA>),
+                                                 SplitTables<K, T>::HA, SplitTables<K, T>::HB,
+                                                 SplitTables<K, T>::AVY, SplitTables<K, T>::PAD>),
                        dim3(tiles_x * tiles_y * nzc), dim3(S::NT),
                        0, st, static_cast<const T*>(x), static_cast<const T*>(b), static_cast<T*>(y),
                        static_cast<const T*>(tab), n, cz, tiles_x, tiles_y);
