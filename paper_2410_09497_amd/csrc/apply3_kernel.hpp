@@ -53,7 +53,13 @@ struct SplitShape {
 // in x and y).
 // AVY: group A forms the Mc_y u_y plane (before its own first rows) and group
 // B only the Mc_x u_x plane, which evens out their LDS reads.
-template <int K, typename T, int CX, int CY, bool RESID, int ROLE, bool GT, bool HOLD, bool AVY, bool PAD>
+// ZP: the z stencils are accumulated forward instead of evaluated from
+// register windows: each plane adds its terms to the rows of the three cell
+// layers it couples to (its own, the one below, the one above), and a layer's
+// rows are written once the plane loop has passed the layer above it.  Three
+// layers of accumulators per output field replace the windows of Mc u, u_z, p
+// and the in-plane partials (about half the registers at high degree).
+template <int K, typename T, int CX, int CY, bool RESID, int ROLE, bool GT, bool HOLD, bool AVY, bool PAD, bool ZP>
 __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__ bvec, T* __restrict__ y,
                                   const T* __restrict__ s_tab, const T* __restrict__ g_tab,
                                   T (*s_u)[4][SplitShape<K, CX, CY, PAD>::PS], T* s_vx, T* s_vy, int n, int L0, int L1,
@@ -157,6 +163,14 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
         q1[0][i] = T(0);
         q1[ROLE == 0 ? 1 : 0][i] = T(0);
     }
+
+    // ZP accumulators: [0] layer Lin-1, [1] layer Lin, [2] layer Lin+1;
+    // group A: y_x, y_y; group B: y_z, y_p
+    T acc0[ZP ? 3 : 1][M], acc1[ZP ? 3 : 1][M];
+#pragma unroll
+    for (int l = 0; l < (ZP ? 3 : 1); ++l)
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc0[l][i] = acc1[l][i] = T(0);
 
     T pf[4][NL];
     const int Zlast = (L1 < n ? L1 + 1 : n) * M - 1;
@@ -279,7 +293,45 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
                 }
                 buf ^= 1;
             }
-            if constexpr (ROLE == 0) {
+            if constexpr (ZP) {
+                if (have) {
+                    // plane c of layer Lin into the rows of layers Lin-1+t, t = 0, 1, 2
+                    const T* zt = ztables();
+                    if constexpr (ROLE == 0) {
+                        acc0[1][c] += r0;
+                        acc1[1][c] += r1;
+                        const T gxv = mdb * r2, gyv = mda * r3;
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) {
+                            const T* LDt = zt + TB::LD + ld_variant(Lin - 1 + t, n) * 3 * M * M;
+#pragma unroll
+                            for (int cc = 0; cc < M; ++cc) {
+                                const T co = LDt[cc * 3 * M + (2 - t) * M + c];
+                                acc0[t][cc] += co * gxv;
+                                acc1[t][cc] += co * gyv;
+                            }
+                        }
+                    } else {
+                        acc1[1][c] += r3;
+                        const T mab = mda * mdb;
+                        const T uzs = mab * r1, ps = mab * r2;
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) {
+#pragma unroll
+                            for (int cc = 0; cc < M; ++cc) {
+                                const int o = (2 - t) * M + c - cc;      // Mc_z, Lc_z column
+                                if (o >= 0 && o <= 2 * M)
+                                    acc0[t][cc] += zt[TB::MC + cc * (2 * M + 1) + o] * r0 +
+                                                   zt[TB::LC + cc * (2 * M + 1) + o] * uzs;
+                                const int od = (1 - t) * M + c;          // D^T_z column
+                                if (od >= 0 && od < 2 * M) acc0[t][cc] -= zt[TB::DT + cc * 2 * M + od] * ps;
+                                const int j = (1 - t) * M + c + 1;       // D_z column
+                                if (j >= 0 && j <= M) acc1[t][cc] -= zt[TB::DD + cc * (M + 1) + j] * uzs;
+                            }
+                        }
+                    }
+                }
+            } else if constexpr (ROLE == 0) {
                 w0[2 * M + c] = r2;
                 w1[2 * M + c] = r3;
                 q0[1][c] = r0;
@@ -307,7 +359,20 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
             for (int c = 0; c < M; ++c) {
                 const int Z = L * M + c;
                 const size_t oz = X + size_t(N1) * (Y + size_t(N1) * Z);
-                if constexpr (ROLE == 0) {
+                if constexpr (ZP) {
+                    const T v0 = acc0[0][c], v1 = acc1[0][c];
+                    if (okxy) {
+                        if constexpr (ROLE == 0) {
+                            const size_t ox = X + size_t(N1 - 1) * (Y + size_t(N1) * Z);
+                            const size_t oy = X + size_t(N1) * (Y + size_t(N1 - 1) * Z);
+                            if (X < N1 - 1) y[ox] = RESID ? bvec[ox] - v0 : v0;
+                            if (Y < N1 - 1) y[nc + oy] = RESID ? bvec[nc + oy] - v1 : v1;
+                        } else {
+                            if (Z < N1 - 1) y[2 * nc + oz] = RESID ? bvec[2 * nc + oz] - v0 : v0;
+                            y[3 * nc + oz] = RESID ? bvec[3 * nc + oz] - v1 : v1;
+                        }
+                    }
+                } else if constexpr (ROLE == 0) {
                     const T* LDz = LD + ld_variant(L, n) * 3 * M * M;
                     T zx = 0, zy = 0;
 #pragma unroll
@@ -343,22 +408,34 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
                 }
             }
         }
-        // 5) slide the windows by one layer
+        // 5) slide the windows (accumulators) by one layer
+        if constexpr (ZP) {
 #pragma unroll
-        for (int i = 0; i < 2 * M; ++i) {
-            w0[i] = w0[i + M];
-            w1[i] = w1[i + M];
-            if constexpr (ROLE == 1) w2[i] = w2[i + M];
-        }
+            for (int i = 0; i < M; ++i) {
+                acc0[0][i] = acc0[1][i];
+                acc0[1][i] = acc0[2][i];
+                acc0[2][i] = T(0);
+                acc1[0][i] = acc1[1][i];
+                acc1[1][i] = acc1[2][i];
+                acc1[2][i] = T(0);
+            }
+        } else {
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-            q0[0][i] = q0[1][i];
-            if constexpr (ROLE == 0) q1[0][i] = q1[1][i];
+            for (int i = 0; i < 2 * M; ++i) {
+                w0[i] = w0[i + M];
+                w1[i] = w1[i + M];
+                if constexpr (ROLE == 1) w2[i] = w2[i + M];
+            }
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                q0[0][i] = q0[1][i];
+                if constexpr (ROLE == 0) q1[0][i] = q1[1][i];
+            }
         }
     }
 }
 
-template <int K, typename T, int CX, int CY, bool RESID, bool GA, bool GB, bool HA, bool HB, bool AVY, bool PAD>
+template <int K, typename T, int CX, int CY, bool RESID, bool GA, bool GB, bool HA, bool HB, bool AVY, bool PAD, bool ZP>
 __global__ void __launch_bounds__((SplitShape<K, CX, CY, PAD>::NT))
 stokes_apply_split_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T* __restrict__ y,
                           const T* __restrict__ tab, int n, int cz, int tiles_x, int tiles_y) {
@@ -380,9 +457,9 @@ stokes_apply_split_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T
     __syncthreads();
     // the groups are whole waves; each runs its copy of the layer loop (same barriers, same order)
     if (threadIdx.x < S::NA)
-        split_loop<K, T, CX, CY, RESID, 0, GA, HA, AVY, PAD>(x, bvec, y, s_tab, tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
+        split_loop<K, T, CX, CY, RESID, 0, GA, HA, AVY, PAD, ZP>(x, bvec, y, s_tab, tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
     else
-        split_loop<K, T, CX, CY, RESID, 1, GB, HB, AVY, PAD>(x, bvec, y, s_tab, tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
+        split_loop<K, T, CX, CY, RESID, 1, GB, HB, AVY, PAD, ZP>(x, bvec, y, s_tab, tab, s_u, s_vx, s_vy, n, L0, L1, X0, Y0);
 }
 
 }  // namespace smg

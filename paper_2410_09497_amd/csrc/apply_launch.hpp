@@ -36,9 +36,11 @@ hipError_t launch_generic(const void* x, const void* b, void* y, const void* tab
 // takes its in-plane stencil rows from (HA / HB: the group holds the rows that
 // stay fixed along its plane loop in registers; GA / GB: the group reads its
 // rows from global memory, otherwise from LDS), whether group A forms the
-// Mc_y u_y plane (AVY), and the padded LDS pitch (PAD).  The fastest of the
-// combinations measured on MI355X at 64^3 cells; holding needs the registers
-// (group A's rows spill in FP64 at degrees 3 and 5).
+// Mc_y u_y plane (AVY), the padded LDS pitch (PAD) and the forward z
+// accumulation (ZP; it removes most of the register spills of FP64 at degree
+// 5, and costs time where nothing spills).  The fastest of the combinations
+// measured on MI355X at 64^3 cells; holding needs the registers (group A's
+// rows spill in FP64 at degrees 3 and 5).
 template <int K, typename T> struct SplitTables {
     static constexpr bool f64 = sizeof(T) == 8;
     static constexpr bool HA = f64 ? K == 2 : (K == 3 || K == 5);
@@ -47,6 +49,7 @@ template <int K, typename T> struct SplitTables {
     static constexpr bool HB = f64 ? K == 2 : K != 4;
     static constexpr bool AVY = f64 ? (K == 2 || K == 3) : (K == 3 || K == 5);
     static constexpr bool PAD = f64 && K == 2;
+    static constexpr bool ZP = f64 && K == 5;
 };
 
 template <int K, typename T, bool RESID, int CX = TileOf<K>::CX, int CY = TileOf<K>::CY>
@@ -59,7 +62,8 @@ hipError_t launch_split(const void* x, const void* b, void* y, const void* tab, 
     const int nzc = (n + cz - 1) / cz;
     hipLaunchKernelGGL((stokes_apply_split_kernel<K, T, CX, CY, RESID, SplitTables<K, T>::GA, SplitTables<K, T>::GB,
                                                  SplitTables<K, T>::HA, SplitTables<K, T>::HB,
-                                                 SplitTables<K, T>::AVY, SplitTables<K, T>::PAD>),
+                                                 SplitTables<K, T>::AVY, SplitTables<K, T>::PAD,
+                                                 SplitTables<K, T>::ZP>),
                        dim3(tiles_x * tiles_y * nzc), dim3(S::NT),
                        0, st, static_cast<const T*>(x), static_cast<const T*>(b), static_cast<T*>(y),
                        static_cast<const T*>(tab), n, cz, tiles_x, tiles_y);
