@@ -75,22 +75,30 @@ def test_apply_multi_tile_multi_chunk(k):
     assert e <= 1e-5 and eu <= 1e-5 and ep <= 1e-5, (k, e, eu, ep)
     r = mg.residual(bd, xd).cpu().numpy()
     assert rel_err(r, b - yref) <= 1e-12
+    r32 = mg.residual(bd.float(), xd.float()).double().cpu().numpy()
+    assert rel_err(r32, b - yref) <= 1e-5
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 def test_apply_full_size_sampled_rows(k):
     """64^3 cells (the benchmark size of every degree): rows sampled across
     the domain, including the first and last rows of every block, computed
-    one by one by the oracle."""
+    one by one by the oracle; the residual form too (the kernels the
+    smoother and FGMRES launch at this size)."""
     torch = need_gpu()
     n = 64
     mg = StokesMG(n, k, n_levels=1)
     S = Stokes(n, k)
     x = uniform_vector(S.ndof, seed=k)
+    b = uniform_vector(S.ndof, seed=50 + k)
     announce("apply full size", f"n={n} k={k}")
     xd = torch.from_numpy(x).cuda()
     y = mg.apply(xd).cpu().numpy()
     y32 = mg.apply(xd.float()).double().cpu().numpy()
+    bd = torch.from_numpy(b).cuda()
+    r = mg.residual(bd, xd).cpu().numpy()
+    r32 = mg.residual(bd.float(), xd.float()).double().cpu().numpy()
+    del bd, xd
     rng = np.random.default_rng(99)
     edges = []
     for o in list(S.offsets) + [S.ndof]:
@@ -100,6 +108,9 @@ def test_apply_full_size_sampled_rows(k):
     scale = np.abs(yref).max()
     assert np.abs(y[rows] - yref).max() <= 1e-12 * scale
     assert np.abs(y32[rows] - yref).max() <= 2e-5 * scale
+    rref = b[rows] - yref
+    assert np.abs(r[rows] - rref).max() <= 1e-12 * scale
+    assert np.abs(r32[rows] - rref).max() <= 2e-5 * scale
 
 
 def test_apply_rejects_bad_arguments():
