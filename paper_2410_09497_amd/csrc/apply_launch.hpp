@@ -43,11 +43,11 @@ hipError_t launch_generic(const void* x, const void* b, void* y, const void* tab
 // rows spill in FP64 at degrees 3 and 5).
 template <int K, typename T> struct SplitTables {
     static constexpr bool f64 = sizeof(T) == 8;
-    static constexpr bool HA = f64 ? K == 2 : (K == 3 || K == 5);
+    static constexpr bool HA = f64 ? (K == 1 || K == 2) : (K == 1 || K == 3 || K == 5);
     static constexpr bool GA = !f64 && K == 2;
     static constexpr bool GB = f64 ? K == 3 : K == 5;
     static constexpr bool HB = f64 ? K == 2 : K != 4;
-    static constexpr bool AVY = f64 ? (K == 2 || K == 3) : (K == 3 || K == 5);
+    static constexpr bool AVY = f64 ? K <= 3 : (K == 1 || K == 3 || K == 5);
     static constexpr bool PAD = f64 && K == 2;
     static constexpr bool ZP = f64 && K == 5;
 };
@@ -71,11 +71,11 @@ hipError_t launch_split(const void* x, const void* b, void* y, const void* tab, 
 }
 
 // Kernel choice per degree and precision: the fastest measured on MI355X at
-// 64^3 cells (HBM-resident).  The split kernel serves degrees 2, 3, 5 and
-// FP32 at degree 4; the single-group kernel with pipelined plane loads
-// serves degree 1 and FP64 at degree 4.
+// 64^3 cells (HBM-resident).  The split kernel serves every degree except
+// FP64 at degree 4, which the single-group kernel with pipelined plane loads
+// serves (the split kernel spills there, with windows or forward sums).
 // (degree 2 also compared 8x4, 6x4, 7x3 and 5x5 tiles and 16-layer chunks for the split kernel: all slower)
-template <int K> constexpr bool split_default(bool f64) { return K == 2 || K == 3 || K == 5 || (K == 4 && !f64); }
+template <int K> constexpr bool split_default(bool f64) { return K != 4 || !f64; }
 
 template <int K, typename T, bool R>
 hipError_t launch_degree_t(bool f64, const void* x, const void* b, void* y, const void* tab, int n, hipStream_t st) {
