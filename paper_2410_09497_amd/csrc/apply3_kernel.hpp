@@ -435,8 +435,10 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
     }
 }
 
+// FP32 at degrees 1 and 2: at least four waves per SIMD (two 8-wave
+// workgroups per CU), so the rows held in registers do not cost occupancy
 template <int K, typename T, int CX, int CY, bool RESID, bool GA, bool GB, bool HA, bool HB, bool AVY, bool PAD, bool ZP>
-__global__ void __launch_bounds__((SplitShape<K, CX, CY, PAD>::NT))
+__global__ void __launch_bounds__((SplitShape<K, CX, CY, PAD>::NT), (sizeof(T) == 4 && K <= 2) ? 4 : 1)
 stokes_apply_split_kernel(const T* __restrict__ x, const T* __restrict__ bvec, T* __restrict__ y,
                           const T* __restrict__ tab, int n, int cz, int tiles_x, int tiles_y) {
     using S = SplitShape<K, CX, CY, PAD>;

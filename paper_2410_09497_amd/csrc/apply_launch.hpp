@@ -40,14 +40,15 @@ hipError_t launch_generic(const void* x, const void* b, void* y, const void* tab
 // accumulation (ZP; it removes most of the register spills of FP64 at degree
 // 5, and costs time where nothing spills).  The fastest of the combinations
 // measured on MI355X at 64^3 cells; holding needs the registers (group A's
-// rows spill in FP64 at degrees 3 and 5).
+// rows spill in FP64 at degrees 3 and 5; in FP32 at degrees 1 and 2 the
+// kernel's launch bounds hold it to 128 VGPRs, two workgroups per CU).
 template <int K, typename T> struct SplitTables {
     static constexpr bool f64 = sizeof(T) == 8;
-    static constexpr bool HA = f64 ? (K == 1 || K == 2) : (K == 1 || K == 3 || K == 5);
-    static constexpr bool GA = !f64 && K == 2;
+    static constexpr bool HA = f64 ? (K == 1 || K == 2) : K != 4;
+    static constexpr bool GA = false;
     static constexpr bool GB = f64 ? K == 3 : K == 5;
     static constexpr bool HB = f64 ? K == 2 : K != 4;
-    static constexpr bool AVY = f64 ? K <= 3 : (K == 1 || K == 3 || K == 5);
+    static constexpr bool AVY = K <= 3 || (!f64 && K == 5);
     static constexpr bool PAD = f64 && K == 2;
     static constexpr bool ZP = f64 && K == 5;
 };
