@@ -4,9 +4,9 @@
 //
 // Group A (the first NA threads, whole waves) owns y_x and y_y of its
 // position: the in-plane rows Lc, D^T and Ld on Mc u, and the z stencil Ld_z
-// on Mc_x u_x and Mc_y u_y from its register windows.  Group B owns y_z and
-// y_p: the in-plane Ld rows on u_z, the divergence rows D u, and the z
-// stencils Mc_z, Lc_z, D^T_z, D_z from its windows; it also forms the shared
+// on Mc_x u_x and Mc_y u_y from its register windows (or forward sums, ZP).
+// Group B owns y_z and y_p: the in-plane Ld rows on u_z, the divergence rows
+// D u, and the z stencils Mc_z, Lc_z, D^T_z, D_z; it also forms the shared
 // Mc_x u_x plane (and the Mc_y u_y plane, unless group A forms it first: AVY)
 // while group A evaluates its first in-plane terms.  Each group runs its own
 // copy of the layer loop, so a thread keeps only its group's windows live
@@ -181,7 +181,7 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
         const bool have = (Lin >= 0) && (Lin < n);
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            T r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0;
+            T r0 = 0, r1 = 0, r2 = 0, r3 = 0;
             if (have) {
                 const int Z = Lin * M + c;
                 T* su = &s_u[buf][0][0];
@@ -342,7 +342,6 @@ __device__ inline void split_loop(const T* __restrict__ x, const T* __restrict__
                 w2[2 * M + c] = r2;
                 q0[1][c] = r3;
             }
-            (void)r4;
         }
 
         // 4) layer Lin-1 is complete: z stencils from the windows, write it
