@@ -155,10 +155,44 @@ __device__ __forceinline__ void contract3(const T* in, T* out, const T* const* S
 }
 
 // v <- A^{-1} v for the three components (in place), work buffer w
+// entries of the velocity vectors per thread: entry idx belongs to thread
+// idx mod NT, as its e-th entry with e = idx div NT
+template <int K, int NTP>
+constexpr int entries_per_thread() {
+    return (3 * PatchShape<K, NTP>::NV + PatchShape<K, NTP>::NT - 1) / PatchShape<K, NTP>::NT;
+}
+
+// rinv[e] = 1 / (lambda_0 + lambda_1 + lambda_2) of this thread's e-th entry:
+// the eigenvalue sums of the fast diagonalization depend only on the patch
+// type, so each thread forms its reciprocals once per patch and the scaling
+// step multiplies instead of dividing
 template <int K, int NTP, typename T>
-__device__ __forceinline__ void fd_inverse(T* v, T* w, const T* const* Sdir, const T* const* Ldir, const int* codes) {
+__device__ inline void fd_reciprocals(T* rinv, const T* const* Ldir, const int* codes) {
     using P = PatchShape<K, NTP>;
-    constexpr int NV = P::NV;
+#pragma unroll
+    for (int e = 0; e < entries_per_thread<K, NTP>(); ++e) {
+        const int idx = threadIdx.x + e * P::NT;
+        rinv[e] = T(0);
+        if (idx < 3 * P::NV) {
+            const int code = codes[idx], c = code_c(code);
+            rinv[e] = T(1) / (Ldir[c * 3 + 0][code_i(code, 0)] + Ldir[c * 3 + 1][code_i(code, 1)] +
+                              Ldir[c * 3 + 2][code_i(code, 2)]);
+        }
+    }
+}
+
+template <int K, int NTP, typename T>
+__device__ __forceinline__ void fd_scale(T* v, const T* rinv) {
+    using P = PatchShape<K, NTP>;
+#pragma unroll
+    for (int e = 0; e < entries_per_thread<K, NTP>(); ++e) {
+        const int idx = threadIdx.x + e * P::NT;
+        if (idx < 3 * P::NV) v[idx] *= rinv[e];
+    }
+}
+
+template <int K, int NTP, typename T>
+__device__ __forceinline__ void fd_inverse(T* v, T* w, const T* const* Sdir, const T* rinv, const int* codes) {
     // a thread per entry: lanes read with unit stride (a thread per 1D line reads
     // fewer words but with strided, bank-conflicting lanes, and measured slower)
     contract3<K, NTP, T, true, 0>(v, w, Sdir, codes);
@@ -167,10 +201,7 @@ __device__ __forceinline__ void fd_inverse(T* v, T* w, const T* const* Sdir, con
     __syncthreads();
     contract3<K, NTP, T, true, 2>(v, w, Sdir, codes);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
-        const int code = codes[idx], c = code_c(code);
-        w[idx] /= Ldir[c * 3 + 0][code_i(code, 0)] + Ldir[c * 3 + 1][code_i(code, 1)] + Ldir[c * 3 + 2][code_i(code, 2)];
-    }
+    fd_scale<K, NTP, T>(w, rinv);
     __syncthreads();
     contract3<K, NTP, T, false, 2>(w, v, Sdir, codes);
     __syncthreads();
@@ -256,18 +287,13 @@ __device__ __forceinline__ void inplane_mfma(const float* in, float* out, const 
 
 // v <- A^{-1} v (FP32) with the in-plane factors on the matrix cores, work buffer w
 template <int K, int NTP>
-__device__ __forceinline__ void fd_inverse_mf(float* v, float* w, const float* const* Sdir, const float* const* Ldir,
+__device__ __forceinline__ void fd_inverse_mf(float* v, float* w, const float* const* Sdir, const float* rinv,
                                      const int* codes, const short* Qm) {
-    using P = PatchShape<K, NTP>;
-    constexpr int NV = P::NV;
     inplane_mfma<K, NTP, true>(v, w, Qm);
     __syncthreads();
     contract3<K, NTP, float, true, 2>(w, v, Sdir, codes);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < 3 * NV; idx += P::NT) {
-        const int code = codes[idx], c = code_c(code);
-        v[idx] /= Ldir[c * 3 + 0][code_i(code, 0)] + Ldir[c * 3 + 1][code_i(code, 1)] + Ldir[c * 3 + 2][code_i(code, 2)];
-    }
+    fd_scale<K, NTP, float>(v, rinv);
     __syncthreads();
     contract3<K, NTP, float, false, 2>(v, w, Sdir, codes);
     __syncthreads();
@@ -428,11 +454,13 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     // per component c and direction d: continuous factors on the diagonal
     const T* Sdir[9] = {SC, SDy, SDz, SDx, SC, SDz, SDx, SDy, SC};
     const T* Ldir[9] = {LC, LDy, LDz, LDx, LC, LDz, LDx, LDy, LC};
+    T rinv[entries_per_thread<K, NTP>()];
+    fd_reciprocals<K, NTP, T>(rinv, Ldir, codes);
     // A^{-1} by fast diagonalization: every product on the vector units, or (MF) the in-plane ones on the
     // matrix cores (inlined: the LDS arrays keep their address space)
     auto a_inverse = [&](T* vv, T* ww) __attribute__((always_inline)) {
-        if constexpr (MF) fd_inverse_mf<K, NTP>(vv, ww, Sdir, Ldir, codes, Qm);
-        else fd_inverse<K, NTP, T>(vv, ww, Sdir, Ldir, codes);
+        if constexpr (MF) fd_inverse_mf<K, NTP>(vv, ww, Sdir, rinv, codes, Qm);
+        else fd_inverse<K, NTP, T>(vv, ww, Sdir, rinv, codes);
     };
     if constexpr (MF) {
         build_inplane<K, NTP>(Qm, Sdir);
