@@ -441,11 +441,14 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     for (int i = tid; i < NP; i += P::NT) R[i] = r[gi.template pres<K>(i)];
     __syncthreads();
 
-    const T* SC = s_tab + PT::SC;
+    // the eigenvector rows: in FP32 read through the vector cache (relieves the LDS pipe, which bounds the kernel),
+    // in FP64 from LDS (there the vector-cache reads were slower; both measured)
+    const T* St = sizeof(T) == 4 ? tab : s_tab;
+    const T* SC = St + PT::SC;
     const T* LC = s_tab + PT::LC;
-    const T* SDx = s_tab + PT::SD + tx * ND * ND;
-    const T* SDy = s_tab + PT::SD + ty * ND * ND;
-    const T* SDz = s_tab + PT::SD + tz * ND * ND;
+    const T* SDx = St + PT::SD + tx * ND * ND;
+    const T* SDy = St + PT::SD + ty * ND * ND;
+    const T* SDz = St + PT::SD + tz * ND * ND;
     const T* LDx = s_tab + PT::LDv + tx * ND;
     const T* LDy = s_tab + PT::LDv + ty * ND;
     const T* LDz = s_tab + PT::LDv + tz * ND;
