@@ -441,10 +441,11 @@ patch_solve_kernel(T* __restrict__ x, const T* __restrict__ r, const T* __restri
     for (int i = tid; i < NP; i += P::NT) R[i] = r[gi.template pres<K>(i)];
     __syncthreads();
 
-    // the eigenvector rows: in FP32 at degrees 1..3 read through the vector cache (relieves the LDS pipe, which
-    // bounds the kernel), otherwise from LDS (there the vector-cache reads were slower; both measured)
+    // the eigenvector rows: at degrees 1..3 those of the continuous direction (SC) in both precisions, and in FP32
+    // all of them, are read through the vector cache (relieves the LDS pipe, which bounds the kernel); the others
+    // from LDS (there the vector-cache reads were slower; all measured)
     const T* St = (sizeof(T) == 4 && K <= 3) ? tab : s_tab;
-    const T* SC = St + PT::SC;
+    const T* SC = (K <= 3 ? tab : s_tab) + PT::SC;
     const T* LC = s_tab + PT::LC;
     const T* SDx = St + PT::SD + tx * ND * ND;
     const T* SDy = St + PT::SD + ty * ND * ND;
